@@ -1,0 +1,191 @@
+/*
+ * ffpluq -- exact rank-profile-revealing PLUQ over Z/pZ on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the shared library libffpluq.so.  Paper: J-G. Dumas, T. Gautier,
+ * C. Pernet, Z. Sultan, "Parallel computation of echelon forms"
+ * (arXiv:1402.3501).  Section 2.1 defines the four routines this library
+ * exports (gemm, trsm, laswp, getrf/PLUQ); Section 3.1 the delayed modular
+ * reduction; Section 4.1 the pivoting that reveals the row and column rank
+ * profiles and the four-quadrant tile recursion.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Matrices are row-major int32 with leading dimension ld >= number of
+ *    columns (ld >= 1).  Entries are canonical residues in [0, p).  Results
+ *    are canonical residues in [0, p).
+ *  - Every matrix / vector pointer is a DEVICE pointer owned by the caller;
+ *    the library never frees or retains caller memory.  Workspace `ws` is a
+ *    caller-owned device buffer of at least the bytes the matching
+ *    *_workspace() query returns (it may be NULL when the query returns 0).
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ *    asynchronous with respect to the host unless stated otherwise.
+ *  - p must be prime.  Path limits: FP64 needs p <= FFP_P_MAX_FP64; INT8
+ *    needs p <= FFP_P_MAX_INT8.  Rank deficiency is not an error.
+ *  - Indices are 0-based int32.
+ *  - Return value: FFP_OK (0), -i when the i-th argument is invalid
+ *    (LAPACK convention, 1-based), or one of the FFP_E_* codes.  On error
+ *    no device memory has been modified unless the code is FFP_E_HIP.
+ *  - The library is thread-compatible: concurrent calls on different
+ *    streams are safe; calls sharing one workspace must not overlap.
+ */
+#ifndef FFPLUQ_H
+#define FFPLUQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *ffp_stream_t; /* hipStream_t */
+
+#define FFP_OK 0
+#define FFP_E_NOTPRIME (-101)    /* p is not prime */
+#define FFP_E_P_RANGE (-102)     /* p too large for the requested path */
+#define FFP_E_WORKSPACE (-103)   /* workspace missing or too small */
+#define FFP_E_HIP (-104)         /* a HIP runtime call failed */
+#define FFP_E_RANGE (-105)       /* an input entry lies outside [0, p) (validating calls only) */
+#define FFP_E_UNSUPPORTED (-106) /* valid request this build does not implement */
+#define FFP_E_NODEVICE (-107)    /* no gfx950 device / kernels failed to load */
+
+/* Largest p of each arithmetic path (see ffp_fgemm). */
+#define FFP_P_MAX_FP64 94906249u /* largest prime with (p-1)^2 + p < 2^53 */
+#define FFP_P_MAX_INT8 16711421u /* largest prime whose centred residues fit 3 signed 8-bit limbs */
+
+typedef enum {
+    FFP_PATH_AUTO = 0, /* fastest exact path for (p, shape) */
+    FFP_PATH_FP64 = 1, /* residues embedded in FP64, FP64 matrix cores */
+    FFP_PATH_INT8 = 2  /* centred residues split in signed 8-bit limbs, INT8 matrix cores */
+} ffp_path;
+
+/* Human-readable name of an error code (static storage). */
+const char *ffp_error_string(int code);
+/* Library version string, e.g. "ffpluq 0.1 gfx950". */
+const char *ffp_version(void);
+/* 1 if p is prime (deterministic Miller-Rabin for 32-bit p), else 0. */
+int ffp_is_prime(uint32_t p);
+/* Number of limbs the INT8 path uses for p (0 if p exceeds FFP_P_MAX_INT8). */
+int ffp_int8_limbs(uint32_t p);
+/* Path FFP_PATH_AUTO resolves to for a product of the given size. */
+int ffp_auto_path(uint32_t p, int64_t m, int64_t n, int64_t k);
+
+/* --------------------------------------------------------------------------
+ * fgemm -- Section 2.1 (gemm): C <- alpha * op(A) * op(B) + beta * C mod p,
+ * with the delayed modular reduction of Section 3.1: products are summed
+ * exactly (FP64: |partial sum| < 2^53; INT8 limbs: |partial sum| < 2^31) and
+ * reduced once at the end, or once per chunk of the inner dimension when k
+ * exceeds the exactness bound.
+ *   transA/transB: 0 = as stored, 1 = transposed.  op(A) is m x k (A stored
+ *   m x k, or k x m when transposed), op(B) is k x n, C is m x n.
+ *   alpha, beta: residues in [0, p).  beta = 0 means C is not read.
+ *   path: ffp_path.  FP64 requires p <= FFP_P_MAX_FP64, INT8 p <= FFP_P_MAX_INT8.
+ * The INT8 path splits A and B into limbs in the workspace.
+ * -------------------------------------------------------------------------- */
+size_t ffp_fgemm_workspace(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t p,
+                           int path);
+int ffp_fgemm(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t p, uint32_t alpha,
+              const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta, int32_t *C,
+              int64_t ldc, int path, void *ws, size_t ws_bytes, ffp_stream_t stream);
+
+/* --------------------------------------------------------------------------
+ * ftrsm -- Section 2.1 (trsm): triangular solve mod p.
+ *   side 0 (left):  B <- alpha * op(T)^-1 * B,  T is m x m;
+ *   side 1 (right): B <- alpha * B * op(T)^-1,  T is n x n;
+ *   uplo 0 lower / 1 upper (the triangle of T that is read),
+ *   trans 0: op(T) = T, 1: op(T) = T^T,
+ *   diag 0 non-unit / 1 unit (the diagonal of T is then not read).
+ * Block recursion onto fgemm (Section 2.1: trsm reduces most work to gemm).
+ * A zero diagonal entry of a non-unit T gives an unspecified result.
+ * -------------------------------------------------------------------------- */
+size_t ffp_ftrsm_workspace(int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+                           uint32_t p, int path);
+int ffp_ftrsm(int side, int uplo, int trans, int diag, int64_t m, int64_t n, uint32_t p,
+              uint32_t alpha, const int32_t *T, int64_t ldt, int32_t *B, int64_t ldb, int path,
+              void *ws, size_t ws_bytes, ffp_stream_t stream);
+
+/* --------------------------------------------------------------------------
+ * flaswp -- Section 2.1 (laswp): permute the rows (dim 0) or columns (dim 1)
+ * of the m x n matrix A in place, given as an index vector rather than a
+ * sequence of swaps (ffp_swaps_to_perm converts):
+ *   dim 0, inverse 0: new row i = old row perm[i]      (perm has m entries)
+ *   dim 0, inverse 1: new row perm[i] = old row i
+ *   dim 1: the same for columns (perm has n entries).
+ * perm must be a permutation (not checked on the device).  Out of place
+ * through the workspace, then copied back.
+ * -------------------------------------------------------------------------- */
+size_t ffp_flaswp_workspace(int dim, int64_t m, int64_t n);
+int ffp_flaswp(int dim, int64_t m, int64_t n, int32_t *A, int64_t lda, const int32_t *perm,
+               int inverse, void *ws, size_t ws_bytes, ffp_stream_t stream);
+
+/* --------------------------------------------------------------------------
+ * pluq -- Section 2.1 (getrf): A = P L U Q with L and U in place of A,
+ * revealing the rank and the row and column rank profiles (Section 4.1),
+ * computed by the four-quadrant tile recursion (Section 4.1, tiled
+ * recursive elimination) with dynamic pivot blocks.
+ * Output (canonical, bit-identical to the reference convention):
+ *   P[i] = original row at position i, Q[j] = original column at position j,
+ *   so A[P[i]][Q[j]] = sum_t L[i][t] U[t][j]; the r pivots come first, in the
+ *   order of the quadrant recursion (top-left, top-right, bottom-left,
+ *   bottom-right, halves rounded down), then the non-pivot rows / columns in
+ *   increasing index.  A holds L strictly below the diagonal of its first r
+ *   columns (unit diagonal implied), U on and above the diagonal of its first
+ *   r rows, and zeros in [r:, r:].
+ *   rank_dev: device int64 receiving r (may be NULL);
+ *   rank_host: host int64 receiving r (may be NULL; the call then returns
+ *     after the factorisation has completed on `stream`);
+ *   rrp / crp: device int32 arrays of min(m, n) entries receiving the sorted
+ *     row / column rank profile in their first r entries (may be NULL).
+ * The host drives the recursion and reads each sub-block's rank back, so
+ * the call synchronises with `stream` internally.
+ * -------------------------------------------------------------------------- */
+size_t ffp_pluq_workspace(int64_t m, int64_t n, uint32_t p, int path);
+int ffp_pluq(int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
+             int64_t *rank_dev, int64_t *rank_host, int32_t *rrp, int32_t *crp, int path, void *ws,
+             size_t ws_bytes, ffp_stream_t stream);
+
+/* --------------------------------------------------------------------------
+ * pluq_batched -- the same factorisation for `batch` independent matrices of
+ * uneven shapes (the heterogeneous pivot blocks of Section 4.1), in one
+ * persistent kernel launch with no host synchronisation (graph-capturable).
+ *   m_arr, n_arr: device int32[batch] shapes (each 0 <= m, n <= FFP_BATCH_MAX_DIM);
+ *   A_off: device int64[batch] element offsets of each row-major matrix
+ *     (leading dimension n_i) in A_packed; P_off / Q_off: device int64[batch]
+ *     offsets of each P (m_i entries) / Q (n_i entries) in P_packed / Q_packed;
+ *   rank_arr: device int32[batch]; rrp_packed / crp_packed use P_off / Q_off
+ *     and receive the sorted profiles in their first r_i entries (may be NULL).
+ *   max_m, max_n: host upper bounds of the shapes (used to size the launch).
+ * Every output equals what ffp_pluq returns for that matrix alone.
+ * -------------------------------------------------------------------------- */
+#define FFP_BATCH_MAX_DIM 1024
+size_t ffp_pluq_batched_workspace(int32_t batch, int32_t max_m, int32_t max_n, uint32_t p, int path);
+int ffp_pluq_batched(int32_t batch, const int32_t *m_arr, const int32_t *n_arr, int32_t max_m,
+                     int32_t max_n, uint32_t p, int32_t *A_packed, const int64_t *A_off,
+                     int32_t *P_packed, const int64_t *P_off, int32_t *Q_packed,
+                     const int64_t *Q_off, int32_t *rank_arr, int32_t *rrp_packed,
+                     int32_t *crp_packed, int path, void *ws, size_t ws_bytes,
+                     ffp_stream_t stream);
+
+/* --------------------------------------------------------------------------
+ * Host helpers (host pointers): conversion between an index vector and the
+ * LAPACK laswp form (sequence of swaps: for i = 0..len-1, swap entries i and
+ * ipiv[i]).  perm[i] = original index placed at position i.
+ * -------------------------------------------------------------------------- */
+int ffp_perm_to_swaps(int64_t len, const int32_t *perm, int32_t *ipiv);
+int ffp_swaps_to_perm(int64_t len, const int32_t *ipiv, int32_t *perm);
+
+/* --------------------------------------------------------------------------
+ * Kernel timing (for benchmarks): when enabled, the library brackets each
+ * launch of its dense product kernels with HIP events on the launching
+ * stream and accumulates, per arithmetic path, the number of launches, the
+ * summed event time and the summed algorithmic work (2*m*n*k field
+ * operations).  Reading synchronises the recorded events.
+ * -------------------------------------------------------------------------- */
+int ffp_profile_enable(int on);
+int ffp_profile_reset(void);
+int ffp_profile_read(int path, int64_t *launches, double *milliseconds, double *field_ops);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FFPLUQ_H */

@@ -1,0 +1,51 @@
+// Device-side exact modular arithmetic shared by the gfx950 kernels.
+//
+// Integers are carried in FP64 registers whenever they stay below 2^53 in
+// magnitude: sums and products of such integers are then exact, which is the
+// delayed-reduction argument of Section 3.1 of the paper (k products of
+// residues are summed exactly while k (p-1)^2 < 2^53).  A reduction is the
+// floor division by p done with one multiplication by 1/p and a correction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ffp {
+
+// canonical residue of an integer-valued double |x| < 2^53
+__device__ __forceinline__ double mod_canon(double x, double p, double pinv) {
+    double q = floor(x * pinv);
+    double r = fma(-q, p, x);  // exact: the true value is a small integer
+    if (r < 0.0) r += p;
+    else if (r >= p) r -= p;
+    return r;
+}
+
+// residue of x in (-p, p) (balanced enough to bound later sums); |x| < 2^53
+__device__ __forceinline__ double mod_near(double x, double p, double pinv) {
+    double q = rint(x * pinv);
+    return fma(-q, p, x);
+}
+
+// centred representative of a canonical residue v in [0, p)
+__device__ __forceinline__ double centre(int32_t v, double p, int32_t half) {
+    return v > half ? (double)v - p : (double)v;
+}
+
+// inverse of a in [1, p) modulo p (p < 2^31), extended Euclid; quotients by
+// correctly rounded FP64 division, whose floor is exact for operands < 2^53
+__device__ __forceinline__ int32_t inv_mod(int32_t a, int32_t p) {
+    int32_t r0 = p, r1 = a, s0 = 0, s1 = 1;
+    while (r1 != 0) {
+        int32_t q = (int32_t)floor((double)r0 / (double)r1);
+        int32_t t = r0 - q * r1;
+        r0 = r1;
+        r1 = t;
+        t = s0 - q * s1;
+        s0 = s1;
+        s1 = t;
+    }
+    return s0 < 0 ? s0 + p : s0;
+}
+
+}  // namespace ffp

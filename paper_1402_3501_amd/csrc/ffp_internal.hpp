@@ -1,0 +1,136 @@
+// Internal declarations of the gfx950 library (not part of the C ABI).
+//
+// Field elements travel as int32 canonical residues in [0, p).  Kernels embed
+// them as *centred* residues c in [-(p-1)/2, (p-1)/2] (FP64 path) or as
+// signed 8-bit limbs of c (INT8 path), accumulate exactly and reduce once
+// (the delayed reduction of Section 3.1 of the paper).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/ffpluq.h"
+
+namespace ffp {
+
+// ------------------------------------------------------------------ errors
+#define FFP_HIP_CHECK(expr)                                  \
+    do {                                                     \
+        hipError_t _e = (expr);                              \
+        if (_e != hipSuccess) return ::ffp::hip_fail(_e, #expr, __FILE__, __LINE__); \
+    } while (0)
+
+#define FFP_CHECK(expr)          \
+    do {                         \
+        int _r = (expr);         \
+        if (_r != FFP_OK) return _r; \
+    } while (0)
+
+int hip_fail(hipError_t e, const char *what, const char *file, int line);
+
+// ------------------------------------------------------------------ field
+struct Field {
+    uint32_t p;
+    double pd;      // p as double
+    double pinv;    // 1/p rounded
+    int64_t half;   // (p-1)/2: residues above it are centred to r - p
+    int64_t kexact; // largest k such that p + k*half^2 < 2^53 (FP64 exact accumulation)
+    int limbs;      // INT8 limbs (0 if p exceeds the INT8 path)
+    explicit Field(uint32_t p_);
+};
+
+bool is_prime_u32(uint32_t p);
+int int8_limbs(uint32_t p);
+
+// ------------------------------------------------------------------ workspace
+// Bump allocator over the caller's workspace (256-byte aligned slices).
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0, peak = 0;
+    bool counting = false;  // size query mode: hand out nullptr, only count
+    void *take(size_t bytes);
+    size_t mark() const { return used; }
+    void release(size_t m) { used = m; }
+};
+
+// ------------------------------------------------------------------ profiling
+struct ProfScope {
+    int path;
+    double ops;
+    hipStream_t s;
+    void *ev0 = nullptr, *ev1 = nullptr;
+    ProfScope(int path_, double ops_, hipStream_t s_);
+    ~ProfScope();
+};
+
+// ------------------------------------------------------------------ kernels (launchers)
+// All return FFP_OK or an error code; all are asynchronous on `s`.
+
+// C <- alpha op(A) op(B) + beta C  (FP64 matrix cores)
+int fgemm_f64(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
+              const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta,
+              int32_t *C, int64_t ldc, hipStream_t s);
+
+// same result through signed 8-bit limbs on INT8 matrix cores (workspace from the arena)
+size_t fgemm_i8_ws(const Field &F, int64_t m, int64_t n, int64_t k);
+int fgemm_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
+             const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta,
+             int32_t *C, int64_t ldc, Arena &ws, hipStream_t s);
+
+// dispatch on path (FFP_PATH_FP64 / FFP_PATH_INT8, AUTO already resolved)
+int fgemm_any(int path, const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k,
+              uint32_t alpha, const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb,
+              uint32_t beta, int32_t *C, int64_t ldc, Arena &ws, hipStream_t s);
+int resolve_path(int path, uint32_t p, int64_t m, int64_t n, int64_t k);
+
+// triangular solve (recursive onto fgemm_any); alpha applied first
+int ftrsm_run(int path, const Field &F, int side, int uplo, int trans, int diag, int64_t m,
+              int64_t n, uint32_t alpha, const int32_t *T, int64_t ldt, int32_t *B, int64_t ldb,
+              Arena &ws, hipStream_t s);
+
+// B <- alpha * B mod p
+int scale_mat(const Field &F, int64_t m, int64_t n, uint32_t alpha, int32_t *B, int64_t ldb,
+              hipStream_t s);
+
+// Permutation described either by an index array or by up to kMaxSeg
+// contiguous segments: destination index d in segment i reads source index
+// src[i] + (d - dst[i]).
+constexpr int kMaxSeg = 8;
+struct SegPerm {
+    int nseg;
+    int64_t dst[kMaxSeg], src[kMaxSeg], len[kMaxSeg];
+};
+struct PermSpec {
+    const int32_t *idx = nullptr;  // if set: dst d reads src idx[d] + idx_base
+    int64_t idx_base = 0;
+    SegPerm seg{};                  // used when idx == nullptr and seg.nseg > 0
+    bool identity() const { return idx == nullptr && seg.nseg == 0; }
+};
+
+// dst[i][j] = src[rp(i)][cp(j)] for an m x n block (out of place)
+int permute_copy(int64_t m, int64_t n, const int32_t *src, int64_t lds, int32_t *dst,
+                 int64_t ldd, const PermSpec &rp, const PermSpec &cp, hipStream_t s);
+// in place through a workspace slice (copy out permuted, copy back)
+int permute_inplace(int64_t m, int64_t n, int32_t *A, int64_t lda, const PermSpec &rp,
+                    const PermSpec &cp, Arena &ws, hipStream_t s);
+// 2-D copy on the stream
+int copy2d(int64_t m, int64_t n, const int32_t *src, int64_t lds, int32_t *dst, int64_t ldd,
+           hipStream_t s);
+
+// PLUQ (host recursion); P, Q device outputs (local indices); returns rank via *r
+int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P,
+             int32_t *Q, int64_t *r, Arena &ws, hipStream_t s);
+size_t pluq_ws(int64_t m, int64_t n, const Field &F, int path);
+// sorted rank profiles from P[0:r] (device); r is a host value
+int rank_profiles(int64_t m, int64_t n, const int32_t *P, const int32_t *Q, int64_t r,
+                  int32_t *rrp, int32_t *crp, Arena &ws, hipStream_t s);
+
+// batched persistent PLUQ
+size_t pluq_batched_ws(int32_t batch, int32_t max_m, int32_t max_n);
+int pluq_batched_run(const Field &F, int32_t batch, const int32_t *m_arr, const int32_t *n_arr,
+                     int32_t max_m, int32_t max_n, int32_t *A, const int64_t *A_off, int32_t *P,
+                     const int64_t *P_off, int32_t *Q, const int64_t *Q_off, int32_t *rank,
+                     int32_t *rrp, int32_t *crp, Arena &ws, hipStream_t s);
+
+}  // namespace ffp

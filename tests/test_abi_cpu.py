@@ -1,0 +1,122 @@
+"""Host-side checks of the C-ABI library (no GPU needed: no kernel is launched).
+
+The library must load, export every function declared in include/ffpluq.h,
+reject invalid arguments with the documented codes before touching the
+device, and convert between index vectors and swap sequences.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1402_3501_amd as ffp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ffpluq.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ffp_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ffp.LIB_PATH):
+        from paper_1402_3501_amd import build
+        build.build()
+    return ffp.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_scalar_helpers(lib):
+    for p in (2, 3, 251, 65521, 131071, 8388593, 94906249, 16711421):
+        assert ffp.is_prime(p)
+    for p in (0, 1, 4, 65535, 131073):
+        assert not ffp.is_prime(p)
+    assert ffp.int8_limbs(251) == 1
+    assert ffp.int8_limbs(65521) == 3 and ffp.int8_limbs(131071) == 3
+    assert ffp.int8_limbs(8388593) == 3
+    assert ffp.int8_limbs(16711421) == 3 and ffp.int8_limbs(16711423 + 2) == 0
+    assert ffp.int8_limbs(2 * 127 * 257 + 1) == 2
+    assert "ffpluq" in ffp.version()
+    assert lib.ffp_error_string(-103) == b"workspace missing or too small"
+
+
+def test_argument_validation_before_device(lib):
+    vp = ctypes.c_void_p
+    fake = vp(0x1000)
+    # negative sizes -> -i
+    assert lib.ffp_fgemm(0, 0, -1, 4, 4, 7, 1, fake, 4, fake, 4, 0, fake, 4, 0, None, 0, None) == -3
+    assert lib.ffp_fgemm(2, 0, 4, 4, 4, 7, 1, fake, 4, fake, 4, 0, fake, 4, 0, None, 0, None) == -1
+    # non-prime and out-of-range p
+    assert lib.ffp_fgemm(0, 0, 4, 4, 4, 9, 1, fake, 4, fake, 4, 0, fake, 4, 0, None, 0, None) == -101
+    assert lib.ffp_fgemm(0, 0, 4, 4, 4, 8388593, 1, fake, 4, fake, 4, 0, fake, 4, 0, None, 0, None) != -102
+    assert lib.ffp_fgemm(0, 0, 4, 4, 4, 2147483647, 1, fake, 4, fake, 4, 0, fake, 4, 1, None, 0, None) == -102
+    assert lib.ffp_fgemm(0, 0, 4, 4, 4, 94906249 + 2 * 3, 1, fake, 4, fake, 4, 0, fake, 4, 1, None, 0,
+                         None) in (-101, -102)
+    assert lib.ffp_fgemm(0, 0, 4, 4, 4, 65537, 1, fake, 4, fake, 4, 0, fake, 4, 2, None, 0, None) != -102
+    assert lib.ffp_fgemm(0, 0, 4, 4, 4, 16777259, 1, fake, 4, fake, 4, 0, fake, 4, 2, None, 0, None) == -102
+    # alpha / beta outside [0, p)
+    assert lib.ffp_fgemm(0, 0, 4, 4, 4, 7, 7, fake, 4, fake, 4, 0, fake, 4, 0, None, 0, None) == -7
+    assert lib.ffp_fgemm(0, 0, 4, 4, 4, 7, 1, fake, 4, fake, 4, 9, fake, 4, 0, None, 0, None) == -12
+    # leading dimensions
+    assert lib.ffp_fgemm(0, 0, 4, 5, 3, 7, 1, fake, 2, fake, 5, 0, fake, 5, 0, None, 0, None) == -9
+    assert lib.ffp_fgemm(0, 0, 4, 5, 3, 7, 1, fake, 3, fake, 4, 0, fake, 5, 0, None, 0, None) == -11
+    assert lib.ffp_fgemm(0, 0, 4, 5, 3, 7, 1, fake, 3, fake, 5, 0, fake, 4, 0, None, 0, None) == -14
+    # bad path
+    assert lib.ffp_fgemm(0, 0, 4, 4, 4, 7, 1, fake, 4, fake, 4, 0, fake, 4, 5, None, 0, None) == -16
+    # empty problems succeed without touching memory
+    assert lib.ffp_fgemm(0, 0, 0, 4, 4, 7, 1, None, 4, None, 4, 0, None, 4, 0, None, 0, None) == 0
+    # ftrsm
+    assert lib.ffp_ftrsm(3, 0, 0, 0, 4, 4, 7, 1, fake, 4, fake, 4, 0, None, 0, None) == -1
+    assert lib.ffp_ftrsm(0, 0, 0, 0, 4, 4, 7, 1, fake, 3, fake, 4, 0, None, 0, None) == -10
+    assert lib.ffp_ftrsm(0, 0, 0, 0, 4, 4, 10, 1, fake, 4, fake, 4, 0, None, 0, None) == -101
+    # flaswp: workspace required
+    assert lib.ffp_flaswp(0, 4, 4, fake, 4, fake, 0, None, 0, None) == -103
+    assert lib.ffp_flaswp(2, 4, 4, fake, 4, fake, 0, None, 0, None) == -1
+    # pluq
+    r = ctypes.c_int64(0)
+    assert lib.ffp_pluq(4, 4, 6, fake, 4, fake, fake, None, ctypes.byref(r), None, None, 0, None, 0,
+                        None) == -101
+    assert lib.ffp_pluq(4, 4, 7, fake, 3, fake, fake, None, ctypes.byref(r), None, None, 0, None, 0,
+                        None) == -5
+    assert lib.ffp_pluq(4, 4, 7, fake, 4, fake, fake, None, ctypes.byref(r), None, None, 0, None, 0,
+                        None) == -103
+    # batched
+    assert lib.ffp_pluq_batched(-1, fake, fake, 4, 4, 7, fake, fake, fake, fake, fake, fake, fake, None,
+                                None, 0, None, 0, None) == -1
+    assert lib.ffp_pluq_batched(3, fake, fake, 2000, 4, 7, fake, fake, fake, fake, fake, fake, fake, None,
+                                None, 0, None, 0, None) == -4
+
+
+def test_workspace_queries(lib):
+    assert lib.ffp_fgemm_workspace(0, 0, 64, 64, 64, 131071, 1) == 0
+    assert lib.ffp_pluq_workspace(512, 512, 65521, 1) >= 512 * 512 * 4
+    assert lib.ffp_flaswp_workspace(0, 100, 50) >= 100 * 50 * 4
+    assert lib.ffp_pluq_workspace(0, 0, 7, 1) > 0
+
+
+def test_perm_swaps_roundtrip(lib):
+    rng = np.random.default_rng(0)
+    for n in (0, 1, 2, 5, 17, 100):
+        perm = rng.permutation(n).astype(np.int32)
+        ipiv = ffp.perm_to_swaps(perm)
+        assert (ipiv >= np.arange(n)).all()
+        # applying the swaps in order to the identity gives back the permutation
+        arr = list(range(n))
+        for i, j in enumerate(ipiv):
+            arr[i], arr[j] = arr[j], arr[i]
+        assert arr == perm.tolist()
+        assert np.array_equal(ffp.swaps_to_perm(ipiv), perm)
+    with pytest.raises(ffp.FFPError):
+        ffp.perm_to_swaps(np.array([0, 0, 1], np.int32))

@@ -1,0 +1,259 @@
+"""GPU parity: every output of the HIP library equals the CPU oracle's, bit for bit.
+
+Sizes span several kernel tiles with ragged tails; primes cover both paths'
+limits and the delayed-reduction regimes (no reduction in the K loop, a
+reduction every few hundred products, one every four).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import checks
+from paper_1402_3501_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+PRIMES = [2, 3, 251, 65521, 131071, 8388593, 94906249]
+
+
+def note(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int32)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def paths_for(p):
+    from paper_1402_3501_amd import PATH_FP64, PATH_INT8, int8_limbs
+    out = []
+    if p <= 94906249:
+        out.append(PATH_FP64)
+    if int8_limbs(p) > 0:
+        out.append(PATH_INT8)
+    return out
+
+
+# ---------------------------------------------------------------- fgemm
+FGEMM_SHAPES = [(1, 1, 1), (7, 5, 3), (64, 64, 16), (130, 70, 33), (257, 300, 129), (200, 513, 700)]
+
+
+@pytest.mark.parametrize("p", PRIMES)
+def test_fgemm_parity(lib, orc, p):
+    rng = np.random.default_rng(p)
+    for path in paths_for(p):
+        for (m, n, k) in FGEMM_SHAPES:
+            for ta, tb in [(0, 0), (1, 0), (0, 1), (1, 1)]:
+                if (m, n, k) == (200, 513, 700) and (ta, tb) != (0, 0):
+                    continue
+                A = rng.integers(0, p, (k, m) if ta else (m, k)).astype(np.int32)
+                B = rng.integers(0, p, (n, k) if tb else (k, n)).astype(np.int32)
+                C = rng.integers(0, p, (m, n)).astype(np.int32)
+                for alpha, beta in [(1, 0), (p - 1, 1), (int(rng.integers(0, p)), int(rng.integers(0, p)))]:
+                    note("fgemm", p, path, m, n, k, ta, tb, alpha, beta)
+                    want = orc.fgemm(A, B, C, p, alpha, beta, bool(ta), bool(tb))
+                    Cd = dev(C)
+                    lib.fgemm(dev(A), dev(B), Cd, p, alpha, beta, bool(ta), bool(tb), path=path)
+                    got = host(Cd)
+                    assert np.array_equal(got, want), (p, path, m, n, k, ta, tb, alpha, beta)
+
+
+def test_fgemm_long_k_reductions(lib, orc):
+    """k far beyond the exactness bound: p = 8388593 needs a reduction every
+    ~512 products, p = 94906249 one every 4."""
+    from paper_1402_3501_amd import PATH_FP64
+    rng = np.random.default_rng(5)
+    for p, k in [(8388593, 2100), (94906249, 300)]:
+        m, n = 70, 90
+        A = rng.integers(0, p, (m, k)).astype(np.int32)
+        B = rng.integers(0, p, (k, n)).astype(np.int32)
+        C = np.zeros((m, n), np.int32)
+        A[:, : k // 2] = p - 1   # worst-case magnitudes
+        B[: k // 2, :] = p - 1
+        note("fgemm long k", p, k)
+        want = orc.fgemm(A, B, C, p, 1, 0)
+        Cd = dev(C)
+        lib.fgemm(dev(A), dev(B), Cd, p, 1, 0, path=PATH_FP64)
+        assert np.array_equal(host(Cd), want)
+
+
+def test_fgemm_submatrix_views(lib, orc):
+    """Operands as strided views (leading dimension > columns, unaligned offsets)."""
+    import torch
+    p = 131071
+    rng = np.random.default_rng(9)
+    big = rng.integers(0, p, (300, 400)).astype(np.int32)
+    G = dev(big)
+    A = G[3:140, 5:70]        # 137 x 65
+    B = G[150:215, 1:200]     # 65 x 199
+    Cbig = torch.zeros((200, 260), dtype=torch.int32, device="cuda")
+    Cv = Cbig[7:144, 31:230]
+    note("fgemm views")
+    lib.fgemm(A, B, Cv, p, 1, 0)
+    want = orc.fgemm(big[3:140, 5:70], big[150:215, 1:200], np.zeros((137, 199), np.int32), p, 1, 0)
+    got = host(Cbig)
+    assert np.array_equal(got[7:144, 31:230], want)
+    assert (got[:7] == 0).all() and (got[144:] == 0).all() and (got[:, :31] == 0).all()
+    assert (got[:, 230:] == 0).all()
+
+
+# ---------------------------------------------------------------- ftrsm
+@pytest.mark.parametrize("p", [3, 65521, 131071, 8388593, 94906249])
+def test_ftrsm_parity(lib, orc, p):
+    rng = np.random.default_rng(p + 1)
+    for path in paths_for(p):
+        for side in (0, 1):
+            for uplo in (0, 1):
+                for trans in (0, 1):
+                    for diag in (0, 1):
+                        for (m, n) in [(5, 3), (70, 33), (200, 129)]:
+                            d = m if side == 0 else n
+                            T = rng.integers(0, p, (d, d)).astype(np.int32)
+                            T[np.arange(d), np.arange(d)] = rng.integers(1, p, d)
+                            B = rng.integers(0, p, (m, n)).astype(np.int32)
+                            alpha = int(rng.integers(1, p))
+                            note("ftrsm", p, path, side, uplo, trans, diag, m, n)
+                            want = orc.ftrsm(side, uplo, trans, diag, T, B, p, alpha)
+                            Bd = dev(B)
+                            lib.ftrsm(side, uplo, trans, diag, dev(T), Bd, p, alpha, path=path)
+                            assert np.array_equal(host(Bd), want), (p, path, side, uplo, trans, diag, m, n)
+
+
+# ---------------------------------------------------------------- flaswp
+def test_flaswp_parity(lib):
+    import torch
+    rng = np.random.default_rng(3)
+    for (m, n) in [(1, 1), (5, 7), (300, 129), (64, 1000)]:
+        A = rng.integers(0, 1 << 30, (m, n)).astype(np.int32)
+        for dim in (0, 1):
+            perm = rng.permutation(m if dim == 0 else n).astype(np.int32)
+            for inverse in (0, 1):
+                note("flaswp", m, n, dim, inverse)
+                Ad = dev(A)
+                lib.flaswp(dim, Ad, torch.from_numpy(perm).cuda(), bool(inverse))
+                got = host(Ad)
+                want = A.copy()
+                if dim == 0:
+                    if inverse:
+                        want[perm] = A
+                    else:
+                        want = A[perm]
+                else:
+                    if inverse:
+                        want[:, perm] = A
+                    else:
+                        want = A[:, perm]
+                assert np.array_equal(got, want)
+                # apply then apply the inverse: identity
+                lib.flaswp(dim, Ad, torch.from_numpy(perm).cuda(), not bool(inverse))
+                assert np.array_equal(host(Ad), A)
+
+
+# ---------------------------------------------------------------- pluq
+def _pluq_compare(lib, orc, A, p, path, tag):
+    note("pluq", tag, A.shape, p, path)
+    want = orc.pluq(A, p, selfcheck=False)
+    Ad = dev(A)
+    res = lib.pluq(Ad, p, path=path)
+    got = host(Ad)
+    assert res.rank == want.rank, (tag, res.rank, want.rank)
+    assert np.array_equal(host(res.P), want.P), tag
+    assert np.array_equal(host(res.Q), want.Q), tag
+    assert np.array_equal(got, want.LU), tag
+    assert np.array_equal(host(res.rrp), want.rrp), tag
+    assert np.array_equal(host(res.crp), want.crp), tag
+
+
+def test_pluq_workload_512(lib, orc):
+    """The 512 x 512 uniform matrix over Z/65521Z, on every path."""
+    A = wl.make("pluq512_p65521")
+    for path in paths_for(65521) + [0]:
+        _pluq_compare(lib, orc, A, 65521, path, "512")
+
+
+@pytest.mark.parametrize("p", [2, 3, 251, 65521, 131071, 8388593, 94906249])
+def test_pluq_random_shapes(lib, orc, p):
+    rng = np.random.default_rng(p * 7 + 1)
+    shapes = [(1, 1), (1, 9), (9, 1), (2, 2), (13, 7), (40, 300), (300, 40), (129, 257), (260, 260),
+              (700, 300), (1, 2000), (1500, 3)]
+    for path in paths_for(p):
+        for (m, n) in shapes:
+            r = int(rng.integers(0, min(m, n) + 1))
+            A = wl.lowrank(m, n, r, p, int(rng.integers(1 << 40)))
+            _pluq_compare(lib, orc, A, p, path, f"lowrank r={r}")
+            if m * n <= 100000:
+                A = rng.integers(0, p, (m, n)).astype(np.int32)
+                _pluq_compare(lib, orc, A, p, path, "uniform")
+
+
+def test_pluq_special_matrices(lib, orc):
+    p = 131071
+    rng = np.random.default_rng(17)
+    cases = {
+        "zero": np.zeros((150, 170), np.int32),
+        "identity": np.eye(300, dtype=np.int32),
+        "rank1": (np.outer(rng.integers(0, p, 333) * (rng.random(333) < 0.3),
+                           rng.integers(0, p, 200) * (rng.random(200) < 0.5)) % p).astype(np.int32),
+    }
+    for n in (5, 130, 600):
+        pi = rng.permutation(n)
+        M = np.zeros((n, n), np.int32)
+        M[np.arange(n), pi] = 1
+        cases[f"perm{n}"] = M
+    # scattered pivots with many empty rows / columns
+    S = np.zeros((400, 500), np.int32)
+    rows = rng.choice(400, 60, replace=False)
+    cols = rng.choice(500, 60, replace=False)
+    S[rows, cols] = rng.integers(1, p, 60)
+    cases["sparse"] = S
+    for tag, A in cases.items():
+        for path in paths_for(p):
+            _pluq_compare(lib, orc, A, p, path, tag)
+
+
+def test_pluq_empty(lib):
+    import torch
+    for (m, n) in [(0, 0), (0, 5), (4, 0)]:
+        A = torch.zeros((m, n), dtype=torch.int32, device="cuda")
+        note("pluq empty", m, n)
+        res = lib.pluq(A, 7)
+        assert res.rank == 0
+        assert np.array_equal(host(res.P), np.arange(m)) and np.array_equal(host(res.Q), np.arange(n))
+
+
+def test_pluq_repeatable(lib):
+    """Bitwise-identical outputs across runs and streams."""
+    import torch
+    p = 65521
+    A = wl.lowrank(900, 700, 350, p, 4242)
+    outs = []
+    for trial in range(3):
+        s = torch.cuda.Stream() if trial == 2 else torch.cuda.current_stream()
+        with torch.cuda.stream(s):
+            Ad = dev(A)
+            note("pluq repeat", trial)
+            res = lib.pluq(Ad, p)
+            outs.append((host(Ad), host(res.P), host(res.Q), res.rank))
+    for o in outs[1:]:
+        assert all(np.array_equal(a, b) for a, b in zip(o[:3], outs[0][:3])) and o[3] == outs[0][3]
+
+
+def test_pluq_checks_medium(lib, orc):
+    """A rank-deficient 2000 x 1800 matrix: compare with the oracle and run the
+    any-size property checks used at full size."""
+    p = 131071
+    A = wl.lowrank(2000, 1800, 900, p, 99)
+    _pluq_compare(lib, orc, A, p, 1, "medium")
+    Ad = dev(A)
+    res = lib.pluq(Ad, p)
+    err = checks.full_check(A, host(Ad), host(res.P), host(res.Q), res.rank, p, orc.order, exact_limit=0)
+    assert err is None, err
