@@ -1,0 +1,199 @@
+"""Benchmark: rank-profile-revealing PLUQ over Z/pZ on one MI355X.
+
+A step is one whole PLUQ of the workload matrix (pluq8192_p131071 by default:
+8192 x 8192, entries uniform mod p = 131071), i.e. one pass of the hot path:
+leaf eliminations, ftrsm, fgemm (Schur updates), flaswp rotations and the
+rank-profile extraction.  The pristine input stays resident in HBM; each step
+starts with a device-to-device copy of it (PLUQ works in place), which costs
+about 0.1% of the step.  value = (2 n^3 / 3) / step time, the paper's
+effective rate.
+
+Also printed (outside the timed steps): the same PLUQ on the other path,
+the 8192^3 fgemm on both paths, and bit-exact agreement between paths.
+
+The roofline object is for the dominant kernel (the modular matrix product),
+from HIP events that the library records around each of its launches on the
+launching stream during the timed steps.  The CPU baseline is the plain
+oracle on a bounded sample (the leading 4096 x 4096 block of the same matrix).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--path auto|fp64|int8]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PLUQ mod p effective Gop/s (2n³/3) + MFMA util; INT8-limb vs FP64, bit-exact"
+PEAK_FP64 = 78.6e12      # dense FP64 matrix peak, MI355X
+PEAK_INT8 = 5.0e15       # dense INT8 matrix peak, MI355X
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--path", default="auto", choices=["auto", "fp64", "int8"])
+    ap.add_argument("--workload", default="pluq8192_p131071")
+    ap.add_argument("--no-extra", action="store_true", help="skip the comparison runs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the factorisation here is not sharded across GPUs "
+              "(see the design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1402_3501_amd as ffp
+    from paper_1402_3501_amd import workloads as wl
+
+    ffp.load()
+    dev = torch.device("cuda:0")
+    spec = wl.WORKLOADS[args.workload]
+    assert spec["kind"] in ("uniform", "lowrank"), "bench workloads are single matrices"
+    m, n, p = spec["m"], spec["n"], spec["p"]
+    path = {"auto": ffp.PATH_AUTO, "fp64": ffp.PATH_FP64, "int8": ffp.PATH_INT8}[args.path]
+    log(f"[bench] generating {args.workload} ...")
+    A_host = wl.make(args.workload)
+    A0 = torch.from_numpy(A_host).to(dev)
+    A = torch.empty_like(A0)
+    P = torch.empty(m, dtype=torch.int32, device=dev)
+    Q = torch.empty(n, dtype=torch.int32, device=dev)
+    k = min(m, n)
+    rrp = torch.empty(k, dtype=torch.int32, device=dev)
+    crp = torch.empty(k, dtype=torch.int32, device=dev)
+    rdev = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(ffp.pluq_workspace(m, n, p, path), dtype=torch.uint8, device=dev)
+    eff_path = path
+    if path == ffp.PATH_AUTO:
+        lib = ffp.load()
+        eff_path = lib.ffp_auto_path(p, m // 2, n // 2, k // 2)
+    limbs = ffp.int8_limbs(p) if eff_path == ffp.PATH_INT8 else 0
+
+    def step():
+        A.copy_(A0)
+        return ffp.pluq_into(A, p, P, Q, rdev, rrp, crp, ws, path=path)
+
+    for i in range(args.warmup):
+        log(f"[bench] warmup {i}")
+        r = step()
+    torch.cuda.synchronize()
+    ffp.profile_reset()
+    ffp.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ffp.profile_enable(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    nominal = 2.0 * n ** 3 / 3.0 if m == n else 2.0 * m * n * k - (m + n) * k * k + 2.0 * k ** 3 / 3.0
+    algorithmic = 2.0 * m * n * r - (m + n) * r * r + 2.0 * r ** 3 / 3.0
+    value = nominal / (ms * 1e-3) / 1e9
+    log(f"[bench] rank {r}  {ms:.2f} ms/step  {value:.1f} Gop/s")
+
+    launches, kms, kops = ffp.profile_read(eff_path)
+    launches_per_step = launches / max(args.steps, 1)
+    if launches and kms > 0:
+        if eff_path == ffp.PATH_INT8:
+            mfma_ops = kops * limbs * limbs
+            roof = {"bound": "mfma", "achieved": mfma_ops / (kms * 1e-3) / 1e12, "peak": PEAK_INT8 / 1e12,
+                    "unit": "TOP/s"}
+        else:
+            roof = {"bound": "mfma", "achieved": kops / (kms * 1e-3) / 1e12, "peak": PEAK_FP64 / 1e12,
+                    "unit": "TFLOP/s"}
+        roof["frac"] = roof["achieved"] / roof["peak"]
+        roof["traffic"] = None
+        roof["kernel"] = "k_fgemm_f64" if eff_path == ffp.PATH_FP64 else "k_fgemm_i8"
+        roof["launches_per_step"] = launches_per_step
+        roof["avg_launch_us"] = kms * 1e3 / launches
+        roof["field_ops_per_launch"] = kops / launches
+        roof["kernel_ms_per_step"] = kms / max(args.steps, 1)
+    else:
+        roof = None
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gop/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i8" if eff_path == ffp.PATH_INT8 else "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "m": m, "n": n, "p": p, "seed": spec["seed"],
+                   "path": "int8" if eff_path == ffp.PATH_INT8 else "fp64", "limbs": limbs or None,
+                   "rank": r, "algorithmic_gops": round(algorithmic / (ms * 1e-3) / 1e9, 3)},
+        "roofline": roof,
+    }
+
+    if not args.no_extra:
+        extra = {}
+        # the other path on the same input: time one run and compare outputs bit for bit
+        ref = (A.clone(), P.clone(), Q.clone(), r)
+        for other in (ffp.PATH_FP64, ffp.PATH_INT8):
+            if other == eff_path or (other == ffp.PATH_INT8 and ffp.int8_limbs(p) == 0):
+                continue
+            ws2 = torch.empty(ffp.pluq_workspace(m, n, p, other), dtype=torch.uint8, device=dev)
+            A.copy_(A0)
+            ffp.pluq_into(A, p, P, Q, rdev, rrp, crp, ws2, path=other)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            A.copy_(A0)
+            r2 = ffp.pluq_into(A, p, P, Q, rdev, rrp, crp, ws2, path=other)
+            torch.cuda.synchronize()
+            t2 = (time.perf_counter() - t0) * 1e3
+            same = bool(r2 == ref[3] and torch.equal(A, ref[0]) and torch.equal(P, ref[1]) and torch.equal(Q, ref[2]))
+            name = "int8" if other == ffp.PATH_INT8 else "fp64"
+            extra[f"pluq_{name}_ms"] = round(t2, 3)
+            extra[f"pluq_{name}_gops"] = round(nominal / (t2 * 1e-3) / 1e9, 3)
+            extra[f"pluq_{name}_bit_exact_vs_primary"] = same
+            del ws2
+        # the n^3 modular product on both paths (same random operands)
+        X = torch.from_numpy(wl.uniform(n, n, p, 102)).to(dev)
+        Y = torch.from_numpy(wl.uniform(n, n, p, 103)).to(dev)
+        results = {}
+        for pth, name in ((ffp.PATH_FP64, "fp64"), (ffp.PATH_INT8, "int8")):
+            if pth == ffp.PATH_INT8 and ffp.int8_limbs(p) == 0:
+                continue
+            Z = torch.zeros((n, n), dtype=torch.int32, device=dev)
+            ffp.fgemm(X, Y, Z, p, path=pth)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 3
+            for _ in range(reps):
+                ffp.fgemm(X, Y, Z, p, path=pth)
+            torch.cuda.synchronize()
+            tg = (time.perf_counter() - t0) * 1e3 / reps
+            extra[f"fgemm{n}_{name}_ms"] = round(tg, 3)
+            extra[f"fgemm{n}_{name}_gops"] = round(2.0 * n ** 3 / (tg * 1e-3) / 1e9, 3)
+            results[name] = Z
+        if len(results) == 2:
+            extra["fgemm_paths_bit_exact"] = bool(torch.equal(results["fp64"], results["int8"]))
+        out["extra"] = extra
+
+    if not args.no_cpu:
+        from oracle import oracle as orc
+        s = 4096 if min(m, n) >= 4096 else min(m, n)
+        sub = np.ascontiguousarray(A_host[:s, :s])
+        log(f"[bench] CPU oracle on a {s}x{s} sample ...")
+        t0 = time.perf_counter()
+        f = orc.pluq(sub, p, selfcheck=False)
+        tc = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(2.0 * s ** 3 / 3.0 / tc / 1e9, 4), "unit": "Gop/s",
+                               "cores": orc.num_threads(), "kind": "oracle",
+                               "sample": f"leading {s}x{s} block of the workload matrix, oracle PLUQ "
+                                         f"(rank {f.rank}), {tc:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -95,10 +95,22 @@ struct ProfRec {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_pool;  // recycled events (creation is the costly part)
 struct ProfTotals {
     int64_t launches = 0;
     double ms = 0.0, ops = 0.0;
 } g_tot[3];
+
+hipEvent_t pool_get() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
 
 void drain_locked() {
     for (auto &r : g_prof) {
@@ -110,8 +122,8 @@ void drain_locked() {
             g_tot[r.path].ms += ms;
             g_tot[r.path].ops += r.ops;
         }
-        (void)hipEventDestroy(r.e0);
-        (void)hipEventDestroy(r.e1);
+        g_pool.push_back(r.e0);
+        g_pool.push_back(r.e1);
     }
     g_prof.clear();
 }
@@ -119,9 +131,13 @@ void drain_locked() {
 
 ProfScope::ProfScope(int path_, double ops_, hipStream_t s_) : path(path_), ops(ops_), s(s_) {
     if (!g_prof_on) return;
-    hipEvent_t a, b;
-    if (hipEventCreate(&a) != hipSuccess) return;
-    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    hipEvent_t a = pool_get(), b = pool_get();
+    if (!a || !b) {
+        if (a) g_pool.push_back(a);
+        if (b) g_pool.push_back(b);
+        return;
+    }
     (void)hipEventRecord(a, s);
     ev0 = a;
     ev1 = b;

@@ -1,18 +1,272 @@
-// fgemm over Z/pZ through signed 8-bit limbs on the INT8 matrix cores.
+// fgemm over Z/pZ on the INT8 matrix cores of gfx950 (v_mfma_i32_16x16x64_i8).
+//
+// The delayed reduction of Section 3.1, carried to 8-bit integers: a
+// canonical residue r is centred (c = r or r - p, |c| <= (p-1)/2) and written
+// in L balanced base-256 digits c = sum_i 256^i c_i with c_i in [-128, 127]
+// (L = 1 for p <= 255, 3 up to p = 16711421).  Then
+//     sum_k a_k b_k = sum_s 256^s S_s,   S_s = sum_{i+j=s} sum_k a_{k,i} b_{k,j},
+// and every S_s is an exact int32 sum of 8-bit products while
+// k * (products per class) * 2^14 < 2^31.  The L^2 digit products run on the
+// INT8 matrix cores with one int32 accumulator per shift class s; the
+// epilogue reduces each S_s, recombines with 256^s mod p, and applies alpha,
+// beta and the store.  Inner dimensions beyond the int32 bound are processed
+// in chunks, each ending in a reduction (beta = 1 for the later chunks).
+//
+// Data path: a split kernel writes the digits of op(A) and op(B) into
+// zero-padded planes [digit][row][k] (k contiguous, so that each lane's
+// 16-byte MFMA operand is one contiguous load); the product kernel computes
+// a 128 x 128 block of C per workgroup, streaming 64-deep K tiles of all L
+// digit planes of both operands through LDS (double buffered) into 8 wave64s,
+// each owning a 32 x 64 sub-block.
 #include "ffp_internal.hpp"
+#include "ffp_device.hpp"
 
 namespace ffp {
 
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int kI8BM = 128, kI8BN = 128, kI8BK = 64;
+constexpr int kI8Threads = 512;
+
+static inline int64_t rup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// ------------------------------------------------------------------ split
+// dst[d][r][kk] = digit d of centre(src(r, kk)), src(r, kk) = X[r*sr + kk*sk],
+// zero outside rows < R, kk < K.  Tile 64 x 64 through LDS so that both the
+// read (along the stored contiguous dimension) and the write (along kk) are
+// coalesced.
+template <int L>
+__global__ __launch_bounds__(256) void k_split(const int32_t *__restrict__ X, int64_t sr, int64_t sk, int64_t R,
+                                               int64_t K, int64_t Kp, int64_t plane, int8_t *__restrict__ dst,
+                                               int32_t half, int32_t p) {
+    __shared__ int32_t tile[64][65];
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.y * 64, k0 = (int64_t)blockIdx.x * 64;
+    const bool along_k = sk == 1;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int idx = tid + e * 256;
+        const int a = idx & 63, b = idx >> 6;   // a runs along the contiguous source dimension
+        const int rr = along_k ? b : a, kk = along_k ? a : b;
+        const int64_t gr = r0 + rr, gk = k0 + kk;
+        int32_t v = 0;
+        if (gr < R && gk < K) {
+            v = X[gr * sr + gk * sk];
+            v = v > half ? v - p : v;  // centred
+        }
+        tile[rr][kk] = v;
+    }
+    __syncthreads();
+    // 64 rows x 16 words (4 digits of consecutive kk per word) per digit plane
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int idx = tid + e * 256;
+        const int w = idx & 15, rr = idx >> 4;
+        uint32_t packed[L];
+#pragma unroll
+        for (int d = 0; d < L; ++d) packed[d] = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int32_t c = tile[rr][w * 4 + q];
+#pragma unroll
+            for (int d = 0; d < L; ++d) {
+                const int32_t dig = (d == L - 1) ? c : (((c + 128) & 255) - 128);
+                packed[d] |= ((uint32_t)(dig & 255)) << (8 * q);
+                c = (c - dig) >> 8;
+            }
+        }
+        const int64_t gr = r0 + rr;
+        uint32_t *out = (uint32_t *)(dst + gr * Kp + k0) + w;
+#pragma unroll
+        for (int d = 0; d < L; ++d) out[(int64_t)d * (plane >> 2)] = packed[d];
+    }
+}
+
+// ------------------------------------------------------------------ product
+template <int L>
+__global__ __launch_bounds__(kI8Threads) void k_fgemm_i8(const int8_t *__restrict__ Ad, const int8_t *__restrict__ Bd,
+                                                        int64_t Kp, int64_t planeA, int64_t planeB, int64_t m,
+                                                        int64_t n, int32_t *__restrict__ C, int64_t ldc, double p,
+                                                        double pinv, double alpha, double beta, double w1,
+                                                        double w2, double w3, double w4) {
+    constexpr int NS = 2 * L - 1;        // shift classes
+    constexpr int BM = kI8BM, BN = kI8BN, BK = kI8BK;
+    constexpr int ROW = BK + 16;         // padded LDS row (bytes)
+    constexpr int WM = 32, WN = 64;      // wave tile (8 waves: 4 x 2)
+    constexpr int FM = WM / 16, FN = WN / 16;
+    __shared__ __attribute__((aligned(16))) int8_t As[2][L][BM][ROW];
+    __shared__ __attribute__((aligned(16))) int8_t Bs[2][L][BN][ROW];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+    const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+
+    // global -> register staging: L*(BM+BN)*BK/16 chunks of 16 bytes
+    constexpr int CH_A = L * BM * BK / 16, CH_B = L * BN * BK / 16;
+    constexpr int PER = (CH_A + CH_B + kI8Threads - 1) / kI8Threads;
+    v4i stage[PER];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int c = tid + e * kI8Threads;
+            if (c < CH_A) {
+                const int d = c / (BM * 4), rem = c % (BM * 4), row = rem >> 2, q = rem & 3;
+                stage[e] = *(const v4i *)(Ad + d * planeA + (m0 + row) * Kp + k0 + q * 16);
+            } else if (c < CH_A + CH_B) {
+                const int cb = c - CH_A;
+                const int d = cb / (BN * 4), rem = cb % (BN * 4), row = rem >> 2, q = rem & 3;
+                stage[e] = *(const v4i *)(Bd + d * planeB + (n0 + row) * Kp + k0 + q * 16);
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int c = tid + e * kI8Threads;
+            if (c < CH_A) {
+                const int d = c / (BM * 4), rem = c % (BM * 4), row = rem >> 2, q = rem & 3;
+                *(v4i *)&As[buf][d][row][q * 16] = stage[e];
+            } else if (c < CH_A + CH_B) {
+                const int cb = c - CH_A;
+                const int d = cb / (BN * 4), rem = cb % (BN * 4), row = rem >> 2, q = rem & 3;
+                *(v4i *)&Bs[buf][d][row][q * 16] = stage[e];
+            }
+        }
+    };
+
+    v4i acc[NS][FM][FN];
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[s][i][j] = v4i{0, 0, 0, 0};
+
+    const int64_t nt = Kp / BK;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int64_t t = 0; t < nt; ++t) {
+        const int buf = (int)(t & 1);
+        if (t + 1 < nt) load((t + 1) * BK);
+        const int kq = (lane >> 4) * 16, r = lane & 15;
+        v4i a[L][FM];
+#pragma unroll
+        for (int d = 0; d < L; ++d)
+#pragma unroll
+            for (int i = 0; i < FM; ++i) a[d][i] = *(const v4i *)&As[buf][d][wm0 + i * 16 + r][kq];
+#pragma unroll
+        for (int db = 0; db < L; ++db) {
+            v4i b[FN];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) b[j] = *(const v4i *)&Bs[buf][db][wn0 + j * 16 + r][kq];
+#pragma unroll
+            for (int da = 0; da < L; ++da)
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[da + db][i][j] =
+                            __builtin_amdgcn_mfma_i32_16x16x64_i8(a[da][i], b[j], acc[da + db][i][j], 0, 0, 0);
+        }
+        if (t + 1 < nt) store(buf ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue: lane l holds rows 4*(l/16)+v, column l%16 of each 16x16 block
+    const double w[5] = {1.0, w1, w2, w3, w4};
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int64_t gj = n0 + wn0 + j * 16 + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t gi = m0 + wm0 + i * 16 + (lane >> 4) * 4 + v;
+                if (gi < m && gj < n) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) t = fma(mod_near((double)acc[s][i][j][v], p, pinv), w[s], t);
+                    double rres = mod_canon(t, p, pinv);
+                    if (alpha != 1.0) rres = mod_canon(alpha * rres, p, pinv);
+                    if (beta != 0.0) {
+                        double c = (double)C[gi * ldc + gj];
+                        if (beta != 1.0) c = mod_canon(beta * c, p, pinv);
+                        rres += c;
+                        if (rres >= p) rres -= p;
+                    }
+                    C[gi * ldc + gj] = (int32_t)rres;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host side
+static int64_t kchunk_for(int L) { return L == 1 ? 131072 : (L == 2 ? 65536 : 32768); }
+
 size_t fgemm_i8_ws(const Field &F, int64_t m, int64_t n, int64_t k) {
-    (void)F; (void)m; (void)n; (void)k;
-    return 0;
+    const int L = F.limbs > 0 ? F.limbs : 3;
+    const int64_t kc = k < kchunk_for(L) ? k : kchunk_for(L);
+    const int64_t Kp = rup(kc > 0 ? kc : 1, kI8BK);
+    return (size_t)L * (size_t)(rup(m, kI8BM) + rup(n, kI8BN)) * (size_t)Kp + 1024;
+}
+
+template <int L>
+static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
+                  const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta, int32_t *C,
+                  int64_t ldc, Arena &ws, hipStream_t s) {
+    const int64_t KC = kchunk_for(L);
+    const int64_t Mp = rup(m, kI8BM), Np = rup(n, kI8BN);
+    double wts[4] = {0, 0, 0, 0};
+    {
+        uint64_t x = 1;
+        for (int i = 0; i < 4; ++i) {
+            x = (x * 256u) % F.p;
+            wts[i] = (double)x;
+        }
+    }
+    for (int64_t kc0 = 0; kc0 < k; kc0 += KC) {
+        const int64_t kc = k - kc0 < KC ? k - kc0 : KC;
+        const int64_t Kp = rup(kc, kI8BK);
+        const size_t mk = ws.mark();
+        const int64_t planeA = Mp * Kp, planeB = Np * Kp;
+        int8_t *Ad = (int8_t *)ws.take((size_t)L * planeA);
+        int8_t *Bd = (int8_t *)ws.take((size_t)L * planeB);
+        if (!Ad || !Bd) return FFP_E_WORKSPACE;
+        // op(A)[i][kk] and op(B)[kk][j] as (row, k) accessors
+        const int32_t *Ab = ta ? A + kc0 * lda : A + kc0;
+        const int32_t *Bb = tb ? B + kc0 : B + kc0 * ldb;
+        const int64_t asr = ta ? 1 : lda, ask = ta ? lda : 1;
+        const int64_t bsr = tb ? ldb : 1, bsk = tb ? 1 : ldb;
+        hipLaunchKernelGGL((k_split<L>), dim3((unsigned)(Kp / 64), (unsigned)(Mp / 64)), dim3(256), 0, s, Ab, asr,
+                           ask, m, kc, Kp, planeA, Ad, (int32_t)F.half, (int32_t)F.p);
+        hipLaunchKernelGGL((k_split<L>), dim3((unsigned)(Kp / 64), (unsigned)(Np / 64)), dim3(256), 0, s, Bb, bsr,
+                           bsk, n, kc, Kp, planeB, Bd, (int32_t)F.half, (int32_t)F.p);
+        const double be = kc0 == 0 ? (double)beta : 1.0;
+        {
+            ProfScope prof(FFP_PATH_INT8, 2.0 * (double)m * (double)n * (double)kc, s);
+            hipLaunchKernelGGL((k_fgemm_i8<L>), dim3((unsigned)(Np / kI8BN), (unsigned)(Mp / kI8BM)), dim3(kI8Threads),
+                               0, s, Ad, Bd, Kp, planeA, planeB, m, n, C, ldc, F.pd, F.pinv, (double)alpha, be,
+                               wts[0], wts[1], wts[2], wts[3]);
+        }
+        FFP_HIP_CHECK(hipGetLastError());
+        ws.release(mk);
+    }
+    return FFP_OK;
 }
 
 int fgemm_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
-             const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta,
-             int32_t *C, int64_t ldc, Arena &ws, hipStream_t s) {
-    (void)ws;
-    return fgemm_f64(F, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s);
+             const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta, int32_t *C,
+             int64_t ldc, Arena &ws, hipStream_t s) {
+    if (m <= 0 || n <= 0) return FFP_OK;
+    if (k <= 0) return fgemm_f64(F, ta, tb, m, n, 0, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    switch (F.limbs) {
+        case 1: return run_i8<1>(F, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws, s);
+        case 2: return run_i8<2>(F, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws, s);
+        case 3: return run_i8<3>(F, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws, s);
+        default: return FFP_E_P_RANGE;
+    }
 }
 
 }  // namespace ffp
