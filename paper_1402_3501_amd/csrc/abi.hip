@@ -17,9 +17,10 @@ int resolve_path(int path, uint32_t p, int64_t m, int64_t n, int64_t k) {
     // one limb: one INT8 product replaces one FP64 product at 64x the peak;
     // three limbs: nine INT8 products, still ~7x the FP64 peak, once the
     // product is large enough to amortise the limb split
-    if (L == 1) return FFP_PATH_INT8;
-    const double work = (double)m * (double)n * (double)k;
-    return (work >= 64.0 * 64.0 * 64.0 && k >= 32) ? FFP_PATH_INT8 : FFP_PATH_FP64;
+    // the limb split costs two extra launches and the INT8 tiles are 128 x 128:
+    // small products stay on the FP64 kernel
+    if (m * n < 256 * 256 || k < 128) return FFP_PATH_FP64;
+    return FFP_PATH_INT8;
 }
 
 int fgemm_any(int path, const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
@@ -225,8 +226,7 @@ int ffp_pluq(int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int32_t 
     if (m > 0 && !P) return -6;
     if (n > 0 && !Q) return -7;
     if (m > INT32_MAX || n > INT32_MAX) return -1;
-    const int eff = pluq_path(path, p, m, n);
-    const size_t need = ffp_pluq_workspace(m, n, p, eff);
+    const size_t need = ffp_pluq_workspace(m, n, p, path);
     if (!ws || ws_bytes < need) return FFP_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     Field F(p);
@@ -234,7 +234,8 @@ int ffp_pluq(int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int32_t 
     ar.base = (char *)ws;
     ar.cap = ws_bytes;
     int64_t r = 0;
-    FFP_CHECK(pluq_run(eff, F, m, n, A, lda, P, Q, &r, ar, s));
+    // with FFP_PATH_AUTO every product inside the factorisation picks its own path
+    FFP_CHECK(pluq_run(path, F, m, n, A, lda, P, Q, &r, ar, s));
     if (rank_dev) {
         hipLaunchKernelGGL(k_set64, dim3(1), dim3(1), 0, s, rank_dev, r);
         FFP_HIP_CHECK(hipGetLastError());

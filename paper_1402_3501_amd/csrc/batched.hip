@@ -1,18 +1,305 @@
-// Batched persistent PLUQ.
+// Batched PLUQ: many independent matrices of uneven shapes and ranks in one
+// persistent launch (the heterogeneous, rank-dependent pivot blocks of
+// Section 4.1 are exactly why the work per matrix cannot be known ahead).
+//
+// Each workgroup repeatedly takes the next matrix from an atomic counter (no
+// host synchronisation; graph-capturable), copies it into its workspace
+// slot, and factors it with the same pivot order as the tile recursion of
+// Section 4.1: the quadrant recursion is walked with an explicit stack to
+// find each pivot (first nonzero of a one-row or one-column region) and the
+// pivot is applied at once as a rank-one update.  Eager and deferred updates
+// give the same Schur complements, so the result equals what ffp_pluq
+// returns for the matrix alone.  The factors are then written back with the
+// final row and column order, together with P, Q, the rank and the sorted
+// rank profiles.
+#include <climits>
+
 #include "ffp_internal.hpp"
+#include "ffp_device.hpp"
 
 namespace ffp {
 
-size_t pluq_batched_ws(int32_t batch, int32_t max_m, int32_t max_n) {
-    (void)batch; (void)max_m; (void)max_n;
-    return 0;
+constexpr int kBT = 256;                      // threads per workgroup
+constexpr int kBMax = FFP_BATCH_MAX_DIM;      // max rows / columns
+constexpr int kBW = kBMax / 32;               // mask words
+constexpr int kBStack = 24;
+
+struct BFrame {
+    uint32_t rows[kBW], cols[kBW], top[kBW], left[kBW];
+    int stage;
+};
+
+struct BShared {
+    uint32_t rowdone[kBW], coldone[kBW], mask[kBW];
+    BFrame st[kBStack];
+    int sp, type, bx, piv, r, job;
+    int rord[kBMax], cord[kBMax];
+    double urow[kBMax], vcol[kBMax];
+    int wcnt[kBW + 1];
+};
+
+enum { BT_FIN = 0, BT_ROW = 1, BT_COL = 2 };
+
+__device__ __forceinline__ bool bbit(const uint32_t *m, int i) { return (m[i >> 5] >> (i & 31)) & 1u; }
+
+__device__ static int bpopc(const uint32_t *m, int nw) {
+    int c = 0;
+    for (int w = 0; w < nw; ++w) c += __popc(m[w]);
+    return c;
+}
+__device__ static int bfirst(const uint32_t *m, int nw) {
+    for (int w = 0; w < nw; ++w)
+        if (m[w]) return w * 32 + __ffs(m[w]) - 1;
+    return -1;
+}
+__device__ static void bfirst_k(const uint32_t *m, int nw, int k, uint32_t *out) {
+    for (int w = 0; w < nw; ++w) {
+        uint32_t x = m[w];
+        const int c = __popc(x);
+        if (k >= c) { out[w] = x; k -= c; }
+        else {
+            uint32_t o = 0;
+            while (k > 0) { const uint32_t low = x & (~x + 1u); o |= low; x ^= low; --k; }
+            out[w] = o;
+        }
+    }
 }
 
-int pluq_batched_run(const Field &F, int32_t batch, const int32_t *m_arr, const int32_t *n_arr,
-                     int32_t max_m, int32_t max_n, int32_t *A, const int64_t *A_off, int32_t *P,
-                     const int64_t *P_off, int32_t *Q, const int64_t *Q_off, int32_t *rank,
-                     int32_t *rrp, int32_t *crp, Arena &ws, hipStream_t s) {
-    return FFP_E_UNSUPPORTED;
+// one thread: walk to the next one-row / one-column region (or finish)
+__device__ static void bwalk(BShared &S, int nwr, int nwc) {
+    while (S.sp > 0) {
+        BFrame &f = S.st[S.sp - 1];
+        if (f.stage == 0) {
+            const int nr = bpopc(f.rows, nwr), nc = bpopc(f.cols, nwc);
+            if (nr == 0 || nc == 0) { S.sp--; continue; }
+            if (nr == 1) {
+                S.type = BT_ROW;
+                S.bx = bfirst(f.rows, nwr);
+                for (int w = 0; w < nwc; ++w) S.mask[w] = f.cols[w];
+                S.sp--;
+                return;
+            }
+            if (nc == 1) {
+                S.type = BT_COL;
+                S.bx = bfirst(f.cols, nwc);
+                for (int w = 0; w < nwr; ++w) S.mask[w] = f.rows[w];
+                S.sp--;
+                return;
+            }
+            bfirst_k(f.rows, nwr, nr / 2, f.top);
+            bfirst_k(f.cols, nwc, nc / 2, f.left);
+            f.stage = 1;
+            BFrame &c = S.st[S.sp++];
+            for (int w = 0; w < nwr; ++w) c.rows[w] = f.top[w];
+            for (int w = 0; w < nwc; ++w) c.cols[w] = f.left[w];
+            c.stage = 0;
+            continue;
+        }
+        bool pushed = false;
+        for (int st = f.stage; st <= 3 && !pushed; ++st) {
+            bool any_r = false, any_c = false;
+            uint32_t cr[kBW], cc[kBW];
+            for (int w = 0; w < nwr; ++w) {
+                const uint32_t top = f.top[w], bot = f.rows[w] & ~f.top[w];
+                cr[w] = st == 1 ? (top & ~S.rowdone[w]) : st == 2 ? bot : (bot & ~S.rowdone[w]);
+                any_r |= cr[w] != 0;
+            }
+            for (int w = 0; w < nwc; ++w) {
+                const uint32_t left = f.left[w], right = f.cols[w] & ~f.left[w];
+                cc[w] = st == 1 ? right : st == 2 ? (left & ~S.coldone[w]) : (right & ~S.coldone[w]);
+                any_c |= cc[w] != 0;
+            }
+            if (any_r && any_c) {
+                f.stage = st + 1;
+                BFrame &c = S.st[S.sp++];
+                for (int w = 0; w < nwr; ++w) c.rows[w] = cr[w];
+                for (int w = 0; w < nwc; ++w) c.cols[w] = cc[w];
+                c.stage = 0;
+                pushed = true;
+            }
+        }
+        if (!pushed) S.sp--;
+    }
+    S.type = BT_FIN;
+}
+
+__global__ void k_batch_reset(int *counter) { *counter = 0; }
+
+__global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32_t *__restrict__ m_arr,
+                                                      const int32_t *__restrict__ n_arr, int32_t *__restrict__ A,
+                                                      const int64_t *__restrict__ A_off, int32_t *__restrict__ P,
+                                                      const int64_t *__restrict__ P_off, int32_t *__restrict__ Q,
+                                                      const int64_t *__restrict__ Q_off, int32_t *__restrict__ rank,
+                                                      int32_t *__restrict__ rrp, int32_t *__restrict__ crp,
+                                                      int *__restrict__ counter, int32_t *__restrict__ slots,
+                                                      int64_t slot_elems, double p, double pinv, int32_t half) {
+    __shared__ BShared S;
+    const int tid = threadIdx.x;
+    int32_t *W = slots + (int64_t)blockIdx.x * slot_elems;
+    while (true) {
+        if (tid == 0) S.job = atomicAdd(counter, 1);
+        __syncthreads();
+        const int job = S.job;
+        if (job >= batch) break;  // uniform: every wave of the workgroup exits
+        const int m = m_arr[job], n = n_arr[job];
+        int32_t *Aj = A + A_off[job];
+        const int nwr = (m + 31) >> 5, nwc = (n + 31) >> 5;
+        // workspace copy (leading dimension n)
+        for (int64_t e = tid; e < (int64_t)m * n; e += kBT) W[e] = Aj[e];
+        if (tid == 0) {
+            for (int w = 0; w < kBW; ++w) { S.rowdone[w] = 0; S.coldone[w] = 0; }
+            BFrame &f = S.st[0];
+            for (int w = 0; w < nwr; ++w) {
+                const int c = m - w * 32;
+                f.rows[w] = c >= 32 ? 0xffffffffu : ((1u << c) - 1u);
+            }
+            for (int w = 0; w < nwc; ++w) {
+                const int c = n - w * 32;
+                f.cols[w] = c >= 32 ? 0xffffffffu : ((1u << c) - 1u);
+            }
+            f.stage = 0;
+            S.sp = (m > 0 && n > 0) ? 1 : 0;
+            S.r = 0;
+        }
+        __syncthreads();
+        while (true) {
+            if (tid == 0) {
+                bwalk(S, nwr, nwc);
+                S.piv = INT_MAX;
+            }
+            __syncthreads();
+            const int type = S.type, bx = S.bx;
+            if (type == BT_FIN) break;
+            // search the region for its first nonzero (entries are canonical residues)
+            if (type == BT_ROW) {
+                for (int c = tid; c < n; c += kBT)
+                    if (bbit(S.mask, c) && W[(int64_t)bx * n + c] != 0) { atomicMin(&S.piv, c); break; }
+            } else {
+                for (int i = tid; i < m; i += kBT)
+                    if (bbit(S.mask, i) && W[(int64_t)i * n + bx] != 0) { atomicMin(&S.piv, i); break; }
+            }
+            __syncthreads();
+            const int pv = S.piv;
+            if (pv == INT_MAX) continue;
+            const int x = type == BT_ROW ? bx : pv, y = type == BT_ROW ? pv : bx;
+            // pivot row (final U entries) and pivot column to LDS
+            for (int c = tid; c < n; c += kBT)
+                if (!bbit(S.coldone, c)) S.urow[c] = (double)W[(int64_t)x * n + c];
+            for (int i = tid; i < m; i += kBT)
+                if (!bbit(S.rowdone, i) && i != x) S.vcol[i] = (double)W[(int64_t)i * n + y];
+            __syncthreads();
+            const double inv = (double)inv_mod((int32_t)S.urow[y], (int32_t)p);
+            // multipliers (final L entries)
+            for (int i = tid; i < m; i += kBT) {
+                if (bbit(S.rowdone, i) || i == x) continue;
+                const double l = mod_canon(S.vcol[i] * inv, p, pinv);
+                S.vcol[i] = l;
+                W[(int64_t)i * n + y] = (int32_t)l;
+            }
+            __syncthreads();
+            // rank-one update of the active block
+            for (int i = 0; i < m; ++i) {
+                if (bbit(S.rowdone, i) || i == x) continue;  // uniform
+                const double l = S.vcol[i];
+                if (l == 0.0) continue;
+                int32_t *row = W + (int64_t)i * n;
+                for (int c = tid; c < n; c += kBT) {
+                    if (c == y || bbit(S.coldone, c)) continue;
+                    row[c] = (int32_t)mod_canon((double)row[c] - l * S.urow[c], p, pinv);
+                }
+            }
+            if (tid == 0) {
+                S.rowdone[x >> 5] |= 1u << (x & 31);
+                S.coldone[y >> 5] |= 1u << (y & 31);
+                S.rord[x] = S.r;
+                S.cord[y] = S.r;
+                S.r += 1;
+            }
+            __syncthreads();
+        }
+        // ---- output order: pivots in order, then the rest ascending
+        const int r = S.r;
+        if (tid == 0) {
+            int acc = 0;
+            for (int w = 0; w < nwr; ++w) {
+                S.wcnt[w] = acc;
+                const int c = m - w * 32;
+                acc += __popc(~S.rowdone[w] & (c >= 32 ? 0xffffffffu : ((1u << c) - 1u)));
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < m; i += kBT) {
+            if (!bbit(S.rowdone, i)) {
+                const uint32_t below = (i & 31) ? (~S.rowdone[i >> 5] & ((1u << (i & 31)) - 1u)) : 0u;
+                S.rord[i] = r + S.wcnt[i >> 5] + __popc(below);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int w = 0; w < nwc; ++w) {
+                S.wcnt[w] = acc;
+                const int c = n - w * 32;
+                acc += __popc(~S.coldone[w] & (c >= 32 ? 0xffffffffu : ((1u << c) - 1u)));
+            }
+        }
+        __syncthreads();
+        for (int c = tid; c < n; c += kBT) {
+            if (!bbit(S.coldone, c)) {
+                const uint32_t below = (c & 31) ? (~S.coldone[c >> 5] & ((1u << (c & 31)) - 1u)) : 0u;
+                S.cord[c] = r + S.wcnt[c >> 5] + __popc(below);
+            }
+        }
+        __syncthreads();
+        for (int64_t e = tid; e < (int64_t)m * n; e += kBT) {
+            const int i = (int)(e / n), c = (int)(e % n);
+            Aj[(int64_t)S.rord[i] * n + S.cord[c]] = W[e];
+        }
+        int32_t *Pj = P + P_off[job], *Qj = Q + Q_off[job];
+        for (int i = tid; i < m; i += kBT) Pj[S.rord[i]] = i;
+        for (int c = tid; c < n; c += kBT) Qj[S.cord[c]] = c;
+        if (tid == 0) {
+            rank[job] = r;
+            if (rrp) {
+                int k = 0;
+                for (int i = 0; i < m; ++i)
+                    if (bbit(S.rowdone, i)) rrp[P_off[job] + k++] = i;
+            }
+            if (crp) {
+                int k = 0;
+                for (int c = 0; c < n; ++c)
+                    if (bbit(S.coldone, c)) crp[Q_off[job] + k++] = c;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+static int batched_grid(int32_t batch) {
+    int g = 512;  // two workgroups per compute unit of an MI355X
+    return batch < g ? batch : g;
+}
+
+size_t pluq_batched_ws(int32_t batch, int32_t max_m, int32_t max_n) {
+    const size_t slot = (size_t)(max_m > 0 ? max_m : 1) * (size_t)(max_n > 0 ? max_n : 1);
+    return 256 + (size_t)batched_grid(batch) * slot * 4 + 256;
+}
+
+int pluq_batched_run(const Field &F, int32_t batch, const int32_t *m_arr, const int32_t *n_arr, int32_t max_m,
+                     int32_t max_n, int32_t *A, const int64_t *A_off, int32_t *P, const int64_t *P_off, int32_t *Q,
+                     const int64_t *Q_off, int32_t *rank, int32_t *rrp, int32_t *crp, Arena &ws, hipStream_t s) {
+    if (batch <= 0) return FFP_OK;
+    int *counter = (int *)ws.take(256);
+    const int grid = batched_grid(batch);
+    const int64_t slot = (int64_t)(max_m > 0 ? max_m : 1) * (int64_t)(max_n > 0 ? max_n : 1);
+    int32_t *slots = (int32_t *)ws.take((size_t)grid * (size_t)slot * 4);
+    if (!counter || !slots) return FFP_E_WORKSPACE;
+    // counter cleared by a kernel (not a memset) so that the sequence can be captured in a graph
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, counter);
+    hipLaunchKernelGGL(k_pluq_batched, dim3(grid), dim3(kBT), 0, s, batch, m_arr, n_arr, A, A_off, P, P_off, Q,
+                       Q_off, rank, rrp, crp, counter, slots, slot, F.pd, F.pinv, (int32_t)F.half);
+    FFP_HIP_CHECK(hipGetLastError());
+    return FFP_OK;
 }
 
 }  // namespace ffp

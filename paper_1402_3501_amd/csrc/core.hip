@@ -66,9 +66,10 @@ Field::Field(uint32_t p_) : p(p_) {
     pinv = 1.0 / pd;
     half = (p - 1) / 2;
     const double two53 = 9007199254740992.0;
-    // p + k * half^2 < 2^53 keeps every partial sum of centred products exact
+    // 2p + k * half^2 < 2^53 keeps every partial sum of centred products exact
+    // when it starts from a value reduced to |x| < 2p
     long double h2 = (long double)(half > 0 ? half : 1) * (long double)(half > 0 ? half : 1);
-    long double kk = ((long double)two53 - 1.0L - (long double)p) / h2;
+    long double kk = ((long double)two53 - 1.0L - 2.0L * (long double)p) / h2;
     kexact = kk > 4.0e18L ? (int64_t)4e18 : (int64_t)kk;
     if (half == 0) kexact = (int64_t)4e18;  // p = 2: every product is 0 or 1
     limbs = int8_limbs(p);

@@ -14,10 +14,11 @@ namespace ffp {
 
 // canonical residue of an integer-valued double |x| < 2^53
 __device__ __forceinline__ double mod_canon(double x, double p, double pinv) {
-    double q = floor(x * pinv);
+    const double q = floor(x * pinv);
     double r = fma(-q, p, x);  // exact: the true value is a small integer
-    if (r < 0.0) r += p;
-    else if (r >= p) r -= p;
+    // q is off by at most one: two selects (no branches) fix it
+    r = r < 0.0 ? r + p : r;
+    r = r >= p ? r - p : r;
     return r;
 }
 
@@ -39,6 +40,50 @@ __device__ __forceinline__ int32_t inv_mod(int32_t a, int32_t p) {
     while (r1 != 0) {
         int32_t q = (int32_t)floor((double)r0 / (double)r1);
         int32_t t = r0 - q * r1;
+        r0 = r1;
+        r1 = t;
+        t = s0 - q * s1;
+        s0 = s1;
+        s1 = t;
+    }
+    return s0 < 0 ? s0 + p : s0;
+}
+
+// same for p < 2^24: all remainders are exact in FP32, the quotient comes from
+// the hardware reciprocal and is corrected by at most a few steps
+__device__ __forceinline__ int32_t inv_mod_small(int32_t a, int32_t p) {
+    int32_t r0 = p, r1 = a, s0 = 0, s1 = 1;
+    while (r1 != 0) {
+        int32_t q = (int32_t)((float)r0 * __builtin_amdgcn_rcpf((float)r1));
+        int32_t t = r0 - q * r1;
+        while (t < 0) { --q; t += r1; }
+        while (t >= r1) { ++q; t -= r1; }
+        r0 = r1;
+        r1 = t;
+        t = s0 - q * s1;
+        s0 = s1;
+        s1 = t;
+    }
+    return s0 < 0 ? s0 + p : s0;
+}
+
+// inverse for a wave-uniform operand, on the scalar unit: quotients by
+// repeated subtraction (most Euclid quotients are 1..3), the hardware
+// reciprocal only for the rare large ones
+__device__ __forceinline__ int32_t inv_mod_uniform(int32_t a, int32_t p) {
+    int32_t r0 = p, r1 = a, s0 = 0, s1 = 1;
+    while (r1 != 0) {
+        int32_t q, t;
+        if (r0 >= (r1 << 3)) {
+            q = (int32_t)((float)r0 * __builtin_amdgcn_rcpf((float)r1));
+            t = r0 - q * r1;
+            while (t < 0) { --q; t += r1; }
+            while (t >= r1) { ++q; t -= r1; }
+        } else {
+            q = 0;
+            t = r0;
+            while (t >= r1) { t -= r1; ++q; }
+        }
         r0 = r1;
         r1 = t;
         t = s0 - q * s1;

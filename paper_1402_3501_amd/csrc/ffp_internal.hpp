@@ -35,7 +35,7 @@ struct Field {
     double pd;      // p as double
     double pinv;    // 1/p rounded
     int64_t half;   // (p-1)/2: residues above it are centred to r - p
-    int64_t kexact; // largest k such that p + k*half^2 < 2^53 (FP64 exact accumulation)
+    int64_t kexact; // largest k such that 2p + k*half^2 < 2^53 (FP64 exact accumulation)
     int limbs;      // INT8 limbs (0 if p exceeds the INT8 path)
     explicit Field(uint32_t p_);
 };
@@ -117,6 +117,10 @@ int permute_inplace(int64_t m, int64_t n, int32_t *A, int64_t lda, const PermSpe
 // 2-D copy on the stream
 int copy2d(int64_t m, int64_t n, const int32_t *src, int64_t lds, int32_t *dst, int64_t ldd,
            hipStream_t s);
+
+// single-wave PLUQ leaf for blocks of at most 64 x 64 (rank to rank_dev)
+int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
+                  int64_t *rank_dev, hipStream_t s);
 
 // PLUQ (host recursion); P, Q device outputs (local indices); returns rank via *r
 int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P,

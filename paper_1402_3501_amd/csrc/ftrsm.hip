@@ -10,59 +10,110 @@
 namespace ffp {
 
 constexpr int kTB = 64;   // base-case triangle size
-constexpr int kTV = 64;   // vectors per workgroup (one per thread)
+constexpr int kTV = 128;  // vectors per workgroup (one per thread)
 
 // Solve, for each of nv independent vectors, x_i = (b_i - sum_{t before i} c(i,t) x_t) / diag_i
-// for i in processing order (ascending if fwd, else descending), where
+// for i in processing order (ascending if FWD, else descending), where
 //   c(i,t) = swap ? T[t][i] : T[i][t]   and   diag_i = unit ? 1 : T[i][i].
-// Vector v, component i lives at B[i][v] (cols_are_vectors) or B[v][i].
-template <bool RED>
+// Vector v, component i lives at B[i][v] (COLS) or B[v][i].
+// One thread per vector.  The coefficients sit in LDS in processing order
+// (zero padded to 64, read as broadcasts).  Components are solved in four
+// groups of 16 held in registers: a group first takes the contributions of
+// the solved groups (kept in LDS, one column per thread), then solves its
+// 16 x 16 diagonal block in registers.
+template <bool RED, bool FWD, bool COLS>
 __global__ __launch_bounds__(kTV) void k_trsm_base(int d, int64_t nv, const int32_t *__restrict__ T,
                                                    int64_t ldt, int32_t *__restrict__ B, int64_t ldb,
-                                                   int fwd, int swap, int unit, int cols_are_vectors,
-                                                   double p, double pinv, int32_t half, int kchunk) {
-    __shared__ double Ts[kTB][kTB];
-    __shared__ double Xs[kTB][kTV + 1];
+                                                   int swap, int unit, double p, double pinv, int32_t half,
+                                                   int kchunk) {
+    constexpr int G = 16;
+    __shared__ __attribute__((aligned(16))) double Ts[kTB][kTB];
     __shared__ double Dinv[kTB];
+    __shared__ double Xs[kTB][kTV + 1];
     const int tid = threadIdx.x;
-    const int64_t v = (int64_t)blockIdx.x * kTV + tid;
     const int32_t ip = (int32_t)p;
 
-    // coefficients in "processing order" positions: row a (a-th processed) holds
-    // c(i_a, i_b) at column b for b < a
-    for (int e = tid; e < d * d; e += kTV) {
-        const int a = e / d, b = e % d;
-        double val = 0.0;
-        if (b < a) {
-            const int i = fwd ? a : d - 1 - a, t = fwd ? b : d - 1 - b;
-            const int32_t c = swap ? T[(int64_t)t * ldt + i] : T[(int64_t)i * ldt + t];
-            val = centre(c, p, half);
+    {
+        // issue all coefficient loads before any use (out-of-triangle and
+        // padding entries read T[0][0] and are zeroed afterwards)
+        constexpr int PER = kTB * kTB / kTV;
+        int32_t cv[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + q * kTV, a = e / kTB, b = e % kTB;
+            const bool in = b < a && a < d;
+            const int i = in ? (FWD ? a : d - 1 - a) : 0, t = in ? (FWD ? b : d - 1 - b) : 0;
+            cv[q] = swap ? T[(int64_t)t * ldt + i] : T[(int64_t)i * ldt + t];
         }
-        Ts[a][b] = val;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + q * kTV, a = e / kTB, b = e % kTB;
+            Ts[a][b] = (b < a && a < d) ? centre(cv[q], p, half) : 0.0;
+        }
     }
-    for (int a = tid; a < d; a += kTV) {
-        const int i = fwd ? a : d - 1 - a;
-        Dinv[a] = unit ? 1.0 : (double)inv_mod(T[(int64_t)i * ldt + i], ip);
+    for (int a = tid; a < kTB; a += kTV) {
+        double dv = 1.0;
+        if (a < d && !unit) {
+            const int i = FWD ? a : d - 1 - a;
+            dv = (double)inv_mod(T[(int64_t)i * ldt + i], ip);
+        }
+        Dinv[a] = dv;
     }
     __syncthreads();
-    if (v < nv) {
-        for (int a = 0; a < d; ++a) {
-            const int i = fwd ? a : d - 1 - a;
-            const int64_t off = cols_are_vectors ? (int64_t)i * ldb + v : v * ldb + i;
-            double acc = 0.0;
-            if (!RED) {
-                for (int b = 0; b < a; ++b) acc = fma(Ts[a][b], Xs[b][tid], acc);
-            } else {
-                int cnt = 0;
-                for (int b = 0; b < a; ++b) {
-                    acc = fma(Ts[a][b], Xs[b][tid], acc);
-                    if (++cnt == kchunk) { acc = mod_near(acc, p, pinv); cnt = 0; }
+    const int64_t v = (int64_t)blockIdx.x * kTV + tid;
+    if (v >= nv) return;
+    int32_t *base = COLS ? B + v : B + v * ldb;
+    const int64_t step = COLS ? ldb : 1;
+    const int ngroups = (d + G - 1) / G;
+#pragma unroll 1
+    for (int J = 0; J < ngroups; ++J) {
+        const int a0 = J * G;
+        double bj[G], acc[G], xg[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const int a = a0 + j;
+            const int i = a < d ? (FWD ? a : d - 1 - a) : 0;
+            bj[j] = (double)base[i * step];
+            acc[j] = 0.0;
+        }
+        // contributions of the groups already solved
+#pragma unroll 1
+        for (int I = 0; I < J; ++I) {
+#pragma unroll
+            for (int t = 0; t < G; ++t) {
+                const double xt = Xs[I * G + t][tid];
+#pragma unroll
+                for (int j = 0; j < G; ++j) acc[j] = fma(Ts[a0 + j][I * G + t], xt, acc[j]);
+                if (RED && ((t + 1) % kchunk == 0)) {
+#pragma unroll
+                    for (int j = 0; j < G; ++j) acc[j] = mod_near(acc[j], p, pinv);
                 }
             }
-            double x = mod_canon((double)B[off] - acc, p, pinv);
-            x = mod_canon(x * Dinv[a], p, pinv);
-            B[off] = (int32_t)x;
-            Xs[a][tid] = x > (double)half ? x - p : x;
+            if (RED) {
+#pragma unroll
+                for (int j = 0; j < G; ++j) acc[j] = mod_near(acc[j], p, pinv);
+            }
+        }
+        // diagonal block
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            double sdiag = 0.0;
+#pragma unroll
+            for (int t = 0; t < j; ++t) {
+                sdiag = fma(Ts[a0 + j][a0 + t], xg[t], sdiag);
+                if (RED && ((t + 1) % kchunk == 0)) sdiag = mod_near(sdiag, p, pinv);
+            }
+            double sj = bj[j] - mod_near(acc[j], p, pinv);
+            sj = mod_canon(sj - sdiag, p, pinv);
+            const double xa = mod_canon(sj * Dinv[a0 + j], p, pinv);
+            bj[j] = xa;
+            xg[j] = xa > (double)half ? xa - p : xa;
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            Xs[a0 + j][tid] = xg[j];
+            const int a = a0 + j;
+            if (a < d) base[(FWD ? a : d - 1 - a) * step] = (int32_t)bj[j];
         }
     }
 }
@@ -70,15 +121,25 @@ __global__ __launch_bounds__(kTV) void k_trsm_base(int d, int64_t nv, const int3
 static int trsm_base(const Field &F, int d, int64_t nv, const int32_t *T, int64_t ldt, int32_t *B,
                      int64_t ldb, bool fwd, bool swap, bool unit, bool cols_are_vectors, hipStream_t s) {
     if (d <= 0 || nv <= 0) return FFP_OK;
-    const bool red = F.kexact < kTB;
+    // exact while 2p + (terms per sum) * half^2 < 2^53: a sum takes at most 48
+    // terms unreduced, else is reduced every kchunk of its terms
+    const bool red = F.kexact < 48;
     const int kchunk = (int)(F.kexact < 1 ? 1 : (F.kexact > kTB ? kTB : F.kexact));
     dim3 grid((unsigned)((nv + kTV - 1) / kTV));
-    if (red)
-        hipLaunchKernelGGL((k_trsm_base<true>), grid, dim3(kTV), 0, s, d, nv, T, ldt, B, ldb, (int)fwd,
-                           (int)swap, (int)unit, (int)cols_are_vectors, F.pd, F.pinv, (int32_t)F.half, kchunk);
-    else
-        hipLaunchKernelGGL((k_trsm_base<false>), grid, dim3(kTV), 0, s, d, nv, T, ldt, B, ldb, (int)fwd,
-                           (int)swap, (int)unit, (int)cols_are_vectors, F.pd, F.pinv, (int32_t)F.half, kchunk);
+#define FFP_TB(R_, F_, C_)                                                                                    \
+    hipLaunchKernelGGL((k_trsm_base<R_, F_, C_>), grid, dim3(kTV), 0, s, d, nv, T, ldt, B, ldb, (int)swap, \
+                       (int)unit, F.pd, F.pinv, (int32_t)F.half, kchunk)
+#define FFP_TB2(R_)                                  \
+    if (fwd) {                                       \
+        if (cols_are_vectors) FFP_TB(R_, true, true); \
+        else FFP_TB(R_, true, false);                \
+    } else {                                         \
+        if (cols_are_vectors) FFP_TB(R_, false, true); \
+        else FFP_TB(R_, false, false);               \
+    }
+    if (red) { FFP_TB2(true) } else { FFP_TB2(false) }
+#undef FFP_TB2
+#undef FFP_TB
     FFP_HIP_CHECK(hipGetLastError());
     return FFP_OK;
 }

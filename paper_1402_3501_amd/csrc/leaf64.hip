@@ -1,0 +1,290 @@
+// PLUQ leaf for blocks of at most 64 x 64, one wave64 per block.
+//
+// Same result as the tile recursion of Section 4.1 applied to the block (see
+// pluq.hip): the quadrant recursion is walked with an explicit stack to find
+// each pivot (first nonzero of a one-row region, or of a one-column region),
+// and each pivot is applied at once as a rank-one update of the remaining
+// block.  The block lives in LDS as FP64-embedded centred residues with
+// delayed reduction (one reduction per element only when the bound of
+// Section 3.1 is reached); lane c owns column c.  Row / column sets are
+// 64-bit masks; the stack is spread over the lanes (lane d holds the frame
+// at depth d) and read with uniform lane indices, so the walk runs on the
+// scalar unit.  The pivot search is one ballot, the inverse one extended
+// Euclid on the pivot.
+#include "ffp_internal.hpp"
+#include "ffp_device.hpp"
+
+namespace ffp {
+
+__device__ __forceinline__ uint64_t rl64(uint64_t v, int lane) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ double rld(double v, int lane) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    return __builtin_bit_cast(double, rl64(b, lane));
+}
+// the first k set bits of x (0 <= k <= popcount(x))
+__device__ __forceinline__ uint64_t first_k64(uint64_t x, int k) {
+    if (k <= 0) return 0;
+    int pos = 0;
+    uint64_t y = x;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const int c = __popcll(y & ((1ull << w) - 1ull));
+        if (k > c) { k -= c; y >>= w; pos += w; }
+    }
+    return pos >= 63 ? x : (x & ((2ull << pos) - 1ull));
+}
+
+enum { B_NONE = 0, B_ROW = 1, B_COL = 2 };
+
+template <bool RED, bool SMALLP>
+__global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restrict__ A, int64_t lda,
+                                              int32_t *__restrict__ P, int32_t *__restrict__ Q,
+                                              int64_t *__restrict__ rank_out, double p, double pinv, int32_t half,
+                                              int64_t kexact) {
+    __shared__ double W[64][65];
+    __shared__ double Lc[64];
+    __shared__ int rord[64], cord[64];
+    const int lane = threadIdx.x;
+    const uint64_t allr = mb >= 64 ? ~0ull : ((1ull << mb) - 1ull);
+    const uint64_t allc = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
+    {
+        // all 64 loads in flight before the first LDS store
+        int32_t av[64];
+        const int cl = lane < nb ? lane : 0;
+#pragma unroll
+        for (int i = 0; i < 64; ++i) av[i] = A[(int64_t)(i < mb ? i : 0) * lda + cl];
+#pragma unroll
+        for (int i = 0; i < 64; ++i) W[i][lane] = (i < mb && lane < nb) ? centre(av[i], p, half) : 0.0;
+    }
+
+    uint64_t rowdone = 0, coldone = 0;
+    int r = 0;
+    int64_t cnt = 0;
+    __syncthreads();
+
+    // ---- generic rank profile: if every diagonal pivot of the unpivoted
+    // elimination is nonzero, the leading minors are all nonzero, the pivots
+    // are (k, k) and the quadrant order is the identity, so no walk and no
+    // search are needed.  A zero pivot sends the block to the general walk.
+    const int kd = mb < nb ? mb : nb;
+    bool generic = true;
+    for (int k = 0; k < kd; ++k) {
+        double u = 0.0;
+        if (lane < nb && lane >= k) {
+            const double c = mod_canon(W[k][lane], p, pinv);
+            u = c > (double)half ? c - p : c;
+            W[k][lane] = u;
+        }
+        double pv = rld(u, k);
+        if (pv < 0.0) pv += p;
+        if (pv == 0.0) { generic = false; break; }
+        const double inv = SMALLP ? (double)inv_mod_uniform((int32_t)pv, (int32_t)p)
+                                  : (double)inv_mod((int32_t)pv, (int32_t)p);
+        double l = 0.0;
+        if (lane > k && lane < mb) {
+            const double c = mod_canon(W[lane][k], p, pinv);
+            const double t = mod_canon(c * inv, p, pinv);
+            l = t > (double)half ? t - p : t;
+            W[lane][k] = l;
+        }
+        Lc[lane] = l;
+        if (lane == 0) { rord[k] = k; cord[k] = k; }
+        __syncthreads();
+        const double uu = (lane > k && lane < nb) ? u : 0.0;
+        const uint64_t act = allr & ~((2ull << k) - 1ull);
+#pragma unroll
+        for (int g = 0; g < 64; g += 32) {
+            if (!((act >> g) & 0xffffffffull)) continue;
+            double wv[32], lv[32];
+#pragma unroll
+            for (int q = 0; q < 32; ++q) {
+                wv[q] = W[g + q][lane];
+                lv[q] = Lc[g + q];
+            }
+#pragma unroll
+            for (int q = 0; q < 32; ++q) wv[q] = fma(-lv[q], uu, wv[q]);
+#pragma unroll
+            for (int q = 0; q < 32; ++q) W[g + q][lane] = wv[q];
+        }
+        if (RED) {
+            if (++cnt >= kexact) {
+                cnt = 0;
+                if (lane > k && lane < nb) {
+                    for (int i = k + 1; i < mb; ++i) W[i][lane] = mod_near(W[i][lane], p, pinv);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (generic) {
+        r = kd;
+        rowdone = kd >= 64 ? ~0ull : ((1ull << kd) - 1ull);
+        coldone = rowdone;
+    } else {
+        // restart from the untouched input with the general walk
+        cnt = 0;
+        int32_t av[64];
+        const int cl = lane < nb ? lane : 0;
+#pragma unroll
+        for (int i = 0; i < 64; ++i) av[i] = A[(int64_t)(i < mb ? i : 0) * lda + cl];
+#pragma unroll
+        for (int i = 0; i < 64; ++i) W[i][lane] = (i < mb && lane < nb) ? centre(av[i], p, half) : 0.0;
+        __syncthreads();
+    }
+    uint64_t f_rows = lane == 0 ? allr : 0, f_cols = lane == 0 ? allc : 0, f_top = 0, f_left = 0;
+    int f_stage = 0;
+    int sp = generic ? 0 : 1;
+
+    while (true) {
+        // ---- walk the quadrant recursion to the next one-row / one-column region
+        int type = B_NONE, bx = 0;
+        uint64_t bmask = 0;
+        while (sp > 0) {
+            const int t = sp - 1;
+            const uint64_t rows = rl64(f_rows, t), cols = rl64(f_cols, t);
+            const int stage = __builtin_amdgcn_readlane(f_stage, t);
+            if (stage == 0) {
+                const int nr = __popcll(rows), nc = __popcll(cols);
+                if (nr == 1) { type = B_ROW; bx = __ffsll((long long)rows) - 1; bmask = cols; --sp; break; }
+                if (nc == 1) { type = B_COL; bx = __ffsll((long long)cols) - 1; bmask = rows; --sp; break; }
+                const uint64_t top = first_k64(rows, nr >> 1), left = first_k64(cols, nc >> 1);
+                if (lane == t) { f_top = top; f_left = left; f_stage = 1; }
+                if (lane == t + 1) { f_rows = top; f_cols = left; f_stage = 0; }
+                ++sp;
+                continue;
+            }
+            // stages 1..3: push the next non-empty child, or pop when none is left
+            const uint64_t top = rl64(f_top, t), left = rl64(f_left, t);
+            bool pushed = false;
+            for (int st = stage; st <= 3 && !pushed; ++st) {
+                uint64_t cr, cc;
+                if (st == 1) { cr = top & ~rowdone; cc = cols & ~left; }
+                else if (st == 2) { cr = rows & ~top; cc = left & ~coldone; }
+                else { cr = rows & ~top & ~rowdone; cc = cols & ~left & ~coldone; }
+                if (cr && cc) {
+                    if (lane == t) f_stage = st + 1;
+                    if (lane == t + 1) { f_rows = cr; f_cols = cc; f_stage = 0; }
+                    ++sp;
+                    pushed = true;
+                }
+            }
+            if (!pushed) --sp;
+        }
+        if (type == B_NONE) break;
+
+        // ---- search: first nonzero of the region
+        int x, y;
+        if (type == B_ROW) {
+            const double v = lane < nb ? W[bx][lane] : 0.0;
+            const bool nz = ((bmask >> lane) & 1ull) && mod_canon(v, p, pinv) != 0.0;
+            const uint64_t b = __ballot(nz);
+            if (!b) continue;
+            x = bx;
+            y = __ffsll((long long)b) - 1;
+        } else {
+            const double v = lane < mb ? W[lane][bx] : 0.0;
+            const bool nz = ((bmask >> lane) & 1ull) && mod_canon(v, p, pinv) != 0.0;
+            const uint64_t b = __ballot(nz);
+            if (!b) continue;
+            x = __ffsll((long long)b) - 1;
+            y = bx;
+        }
+
+        // ---- pivot row (final U entries, reduced and centred)
+        const bool cact = lane < nb && !((coldone >> lane) & 1ull);
+        double u = 0.0;
+        if (cact) {
+            const double c = mod_canon(W[x][lane], p, pinv);
+            u = c > (double)half ? c - p : c;
+            W[x][lane] = u;
+        }
+        double pv = rld(u, y);
+        if (pv < 0.0) pv += p;
+        const double inv = SMALLP ? (double)inv_mod_uniform((int32_t)pv, (int32_t)p)
+                                  : (double)inv_mod((int32_t)pv, (int32_t)p);
+        // ---- multipliers (final L entries)
+        const bool ract = lane < mb && lane != x && !((rowdone >> lane) & 1ull);
+        double l = 0.0;
+        if (ract) {
+            const double c = mod_canon(W[lane][y], p, pinv);
+            const double t = mod_canon(c * inv, p, pinv);
+            l = t > (double)half ? t - p : t;
+            W[lane][y] = l;
+        }
+        Lc[lane] = l;
+        if (lane == 0) { rord[x] = r; cord[y] = r; }
+        __syncthreads();
+        // ---- rank-one update of the active block, 32 rows at a time: all
+        // loads of a half are issued before any of its stores
+        const double uu = (cact && lane != y) ? u : 0.0;
+        const uint64_t act = allr & ~rowdone & ~(1ull << x);
+#pragma unroll
+        for (int g = 0; g < 64; g += 32) {
+            if (!((act >> g) & 0xffffffffull)) continue;
+            double wv[32], lv[32];
+#pragma unroll
+            for (int q = 0; q < 32; ++q) {
+                wv[q] = W[g + q][lane];
+                lv[q] = Lc[g + q];
+            }
+#pragma unroll
+            for (int q = 0; q < 32; ++q) wv[q] = fma(-lv[q], uu, wv[q]);
+#pragma unroll
+            for (int q = 0; q < 32; ++q) W[g + q][lane] = wv[q];
+        }
+        if (RED) {
+            if (++cnt >= kexact) {
+                cnt = 0;
+                if (cact && lane != y) {
+                    uint64_t a2 = act;
+                    while (a2) {
+                        const int i = __ffsll((long long)a2) - 1;
+                        a2 &= a2 - 1;
+                        W[i][lane] = mod_near(W[i][lane], p, pinv);
+                    }
+                }
+            }
+        }
+        rowdone |= 1ull << x;
+        coldone |= 1ull << y;
+        ++r;
+        __syncthreads();
+    }
+
+    // ---- outputs: pivots in order, then the other rows / columns ascending
+    if (lane < mb && !((rowdone >> lane) & 1ull))
+        rord[lane] = r + __popcll(~rowdone & allr & ((1ull << lane) - 1ull));
+    if (lane < nb && !((coldone >> lane) & 1ull))
+        cord[lane] = r + __popcll(~coldone & allc & ((1ull << lane) - 1ull));
+    __syncthreads();
+    if (lane < nb) {
+        const int cp = cord[lane];
+        for (int i = 0; i < mb; ++i) A[(int64_t)rord[i] * lda + cp] = (int32_t)mod_canon(W[i][lane], p, pinv);
+        Q[cp] = lane;
+    }
+    if (lane < mb) P[rord[lane]] = lane;
+    if (lane == 0) *rank_out = r;
+}
+
+int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
+                  int64_t *rank_dev, hipStream_t s) {
+    const bool red = F.kexact < 64;
+    const bool small = F.p < (1u << 24);
+#define FFP_L64(R_, S_)                                                                                      \
+    hipLaunchKernelGGL((k_leaf64<R_, S_>), dim3(1), dim3(64), 0, s, (int)m, (int)n, A, lda, P, Q, rank_dev, F.pd, \
+                       F.pinv, (int32_t)F.half, F.kexact)
+    if (red) {
+        if (small) FFP_L64(true, true); else FFP_L64(true, false);
+    } else {
+        if (small) FFP_L64(false, true); else FFP_L64(false, false);
+    }
+#undef FFP_L64
+    FFP_HIP_CHECK(hipGetLastError());
+    return FFP_OK;
+}
+
+}  // namespace ffp

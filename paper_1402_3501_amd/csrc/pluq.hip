@@ -31,8 +31,11 @@ constexpr int kLMaxDim = 1024;  // max rows / columns of a leaf
 constexpr int kLW = kLMaxDim / 32;
 constexpr int kLStack = 24;
 
+// blocks up to 64 x 64 go to the single-wave leaf; the register-tiled
+// workgroup leaf takes skinny blocks (one side at most 32) that fit it
+static inline bool leaf64_fits(int64_t m, int64_t n) { return m >= 1 && n >= 1 && m <= 64 && n <= 64; }
 static inline bool leaf_fits(int64_t m, int64_t n) {
-    return m >= 1 && n >= 1 && m <= kLMaxDim && n <= kLMaxDim &&
+    return m >= 1 && n >= 1 && m <= kLMaxDim && n <= kLMaxDim && (m <= 32 || n <= 32) &&
            ((m + kLTile - 1) / kLTile) * ((n + kLTile - 1) / kLTile) <= kLT;
 }
 
@@ -491,6 +494,10 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
         return FFP_OK;
     }
     const Field &F = *c.F;
+    if (leaf64_fits(m, n)) {
+        FFP_CHECK(leaf64_launch(F, m, n, A, lda, P, Q, c.rank_dev, s));
+        return read_rank(c.rank_dev, rank, s);
+    }
     if (leaf_fits(m, n)) {
         const bool red = F.kexact < kLMaxDim;
         if (red)
