@@ -132,7 +132,6 @@ size_t ffp_ftrsm_workspace(int side, int uplo, int trans, int diag, int64_t m, i
     if (p < 2 || m < 0 || n < 0) return 0;
     const int64_t d = side == 0 ? m : n, nv = side == 0 ? n : m;
     const int eff = resolve_path(path, p, d / 2, nv, d / 2);
-    if (eff != FFP_PATH_INT8 || int8_limbs(p) == 0) return 0;
     Field F(p);
     Arena ar;
     ar.counting = true;
@@ -159,7 +158,7 @@ int ffp_ftrsm(int side, int uplo, int trans, int diag, int64_t m, int64_t n, uin
     if (ldb < (n > 1 ? n : 1)) return -12;
     const int64_t nv = side == 0 ? n : m;
     const int eff = resolve_path(path, p, d / 2, nv, d / 2);
-    const size_t need = ffp_ftrsm_workspace(side, uplo, trans, diag, m, n, p, eff);
+    const size_t need = ffp_ftrsm_workspace(side, uplo, trans, diag, m, n, p, path);
     if (need > 0 && (!ws || ws_bytes < need)) return FFP_E_WORKSPACE;
     Field F(p);
     Arena ar;

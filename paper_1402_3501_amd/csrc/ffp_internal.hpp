@@ -118,9 +118,10 @@ int permute_inplace(int64_t m, int64_t n, int32_t *A, int64_t lda, const PermSpe
 int copy2d(int64_t m, int64_t n, const int32_t *src, int64_t lds, int32_t *dst, int64_t ldd,
            hipStream_t s);
 
-// single-wave PLUQ leaf for blocks of at most 64 x 64 (rank to rank_dev)
+// single-wave PLUQ leaf for blocks of at most 64 x 64 (rank to rank_dev);
+// with gflag non-null: generic-only mode (see leaf64.hip)
 int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
-                  int64_t *rank_dev, hipStream_t s);
+                  int64_t *rank_dev, int *gflag, hipStream_t s);
 
 // PLUQ (host recursion); P, Q device outputs (local indices); returns rank via *r
 int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P,

@@ -40,11 +40,16 @@ __device__ __forceinline__ uint64_t first_k64(uint64_t x, int k) {
 
 enum { B_NONE = 0, B_ROW = 1, B_COL = 2 };
 
-template <bool RED, bool SMALLP>
+// GEN: generic-only mode used by the speculative factorisation: a zero
+// diagonal pivot sets *gflag and leaves the block untouched; nothing runs once
+// *gflag is set; P, Q and the rank are not written (they are the identity and
+// min(mb, nb)).
+template <bool RED, bool SMALLP, bool GEN>
 __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restrict__ A, int64_t lda,
                                               int32_t *__restrict__ P, int32_t *__restrict__ Q,
                                               int64_t *__restrict__ rank_out, double p, double pinv, int32_t half,
-                                              int64_t kexact) {
+                                              int64_t kexact, int *__restrict__ gflag) {
+    if (GEN && __builtin_amdgcn_readfirstlane(*(volatile int *)gflag) != 0) return;
     __shared__ double W[64][65];
     __shared__ double Lc[64];
     __shared__ int rord[64], cord[64];
@@ -119,6 +124,12 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
             }
         }
         __syncthreads();
+    }
+    if (GEN) {
+        if (!generic) {
+            if (threadIdx.x == 0) *gflag = 1;
+            return;
+        }
     }
     if (generic) {
         r = kd;
@@ -264,24 +275,29 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
     if (lane < nb) {
         const int cp = cord[lane];
         for (int i = 0; i < mb; ++i) A[(int64_t)rord[i] * lda + cp] = (int32_t)mod_canon(W[i][lane], p, pinv);
-        Q[cp] = lane;
+        if (!GEN) Q[cp] = lane;
     }
-    if (lane < mb) P[rord[lane]] = lane;
-    if (lane == 0) *rank_out = r;
+    if (!GEN) {
+        if (lane < mb) P[rord[lane]] = lane;
+        if (lane == 0) *rank_out = r;
+    }
 }
 
 int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
-                  int64_t *rank_dev, hipStream_t s) {
+                  int64_t *rank_dev, int *gflag, hipStream_t s) {
     const bool red = F.kexact < 64;
     const bool small = F.p < (1u << 24);
-#define FFP_L64(R_, S_)                                                                                      \
-    hipLaunchKernelGGL((k_leaf64<R_, S_>), dim3(1), dim3(64), 0, s, (int)m, (int)n, A, lda, P, Q, rank_dev, F.pd, \
-                       F.pinv, (int32_t)F.half, F.kexact)
-    if (red) {
-        if (small) FFP_L64(true, true); else FFP_L64(true, false);
-    } else {
-        if (small) FFP_L64(false, true); else FFP_L64(false, false);
+#define FFP_L64(R_, S_, G_)                                                                                      \
+    hipLaunchKernelGGL((k_leaf64<R_, S_, G_>), dim3(1), dim3(64), 0, s, (int)m, (int)n, A, lda, P, Q, rank_dev, \
+                       F.pd, F.pinv, (int32_t)F.half, F.kexact, gflag)
+#define FFP_L64G(G_)                                                       \
+    if (red) {                                                             \
+        if (small) FFP_L64(true, true, G_); else FFP_L64(true, false, G_); \
+    } else {                                                               \
+        if (small) FFP_L64(false, true, G_); else FFP_L64(false, false, G_); \
     }
+    if (gflag) { FFP_L64G(true) } else { FFP_L64G(false) }
+#undef FFP_L64G
 #undef FFP_L64
     FFP_HIP_CHECK(hipGetLastError());
     return FFP_OK;

@@ -15,9 +15,11 @@
 // Eager and deferred updates give the same Schur complements, so the leaf
 // returns exactly what the block recursion would.
 #include <algorithm>
+#include <cstdlib>
 #include <climits>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "ffp_internal.hpp"
 #include "ffp_device.hpp"
@@ -431,6 +433,37 @@ int read_rank(const int64_t *dev, int64_t *out, hipStream_t s) {
     return FFP_OK;
 }
 
+// A second stream (one per device, default priority) for the triangular
+// solve E = C1 U1^-1 and the product G -= E V1, which are independent of
+// D = L1^-1 B1: the two latency-bound solve chains then overlap.
+std::mutex g_side_mu;
+hipStream_t g_side[64];
+std::vector<hipEvent_t> g_evpool;
+
+int side_stream(hipStream_t *out) {
+    int dev = 0;
+    FFP_HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(g_side_mu);
+    if (dev < 0 || dev >= 64) return FFP_E_UNSUPPORTED;
+    if (!g_side[dev]) FFP_HIP_CHECK(hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking));
+    *out = g_side[dev];
+    return FFP_OK;
+}
+int ev_get(hipEvent_t *e) {
+    std::lock_guard<std::mutex> g(g_side_mu);
+    if (!g_evpool.empty()) {
+        *e = g_evpool.back();
+        g_evpool.pop_back();
+        return FFP_OK;
+    }
+    FFP_HIP_CHECK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    return FFP_OK;
+}
+void ev_put(hipEvent_t e) {
+    std::lock_guard<std::mutex> g(g_side_mu);
+    g_evpool.push_back(e);
+}
+
 PermSpec by_index(const int32_t *idx) {
     PermSpec ps;
     ps.idx = idx;
@@ -455,6 +488,47 @@ int trsm_sub(Ctx &c, int side, int uplo, int diag, int64_t m, int64_t n, const i
              int32_t *B, int64_t ldb) {
     if (m <= 0 || n <= 0) return FFP_OK;
     return ftrsm_run(c.path, *c.F, side, uplo, 0, diag, m, n, 1, T, ldt, B, ldb, *c.ws, c.s);
+}
+
+// D = L1^-1 B1 (main stream), E = C1 U1^-1 then G -= E V1 (side stream),
+// then [F; H] -= [M1; E] D after both (A1 = L1\U1 holds r1 pivots).
+int node_updates(Ctx &c, int64_t m, int64_t n, int64_t m1, int64_t n1, int64_t r1, int32_t *A, int64_t lda) {
+    if (r1 <= 0) return FFP_OK;
+    const Field &F = *c.F;
+    Arena &ws = *c.ws;
+    hipStream_t s2;
+    FFP_CHECK(side_stream(&s2));
+    // workspace of the side stream, reserved until the join
+    size_t need = 0;
+    if (c.path != FFP_PATH_FP64 && F.limbs > 0) {
+        const size_t a = fgemm_i8_ws(F, m - m1, r1, r1), b = fgemm_i8_ws(F, m - m1, n1 - r1, r1);
+        need = (a > b ? a : b) + 1024;
+    }
+    const size_t mk = ws.mark();
+    Arena a2;
+    if (need) {
+        a2.base = (char *)ws.take(need);
+        a2.cap = need;
+        if (!a2.base) return FFP_E_WORKSPACE;
+    }
+    hipEvent_t fork, join;
+    FFP_CHECK(ev_get(&fork));
+    FFP_CHECK(ev_get(&join));
+    FFP_HIP_CHECK(hipEventRecord(fork, c.s));
+    FFP_HIP_CHECK(hipStreamWaitEvent(s2, fork, 0));
+    Ctx c2 = c;
+    c2.s = s2;
+    c2.ws = &a2;
+    FFP_CHECK(trsm_sub(c2, 1, 1, 0, m - m1, r1, A, lda, A + m1 * lda, lda));                         // E
+    FFP_CHECK(fgemm_sub(c2, m - m1, n1 - r1, r1, A + m1 * lda, lda, A + r1, lda, A + m1 * lda + r1, lda));  // G
+    FFP_HIP_CHECK(hipEventRecord(join, s2));
+    FFP_CHECK(trsm_sub(c, 0, 0, 1, r1, n - n1, A, lda, A + n1, lda));                                // D
+    FFP_HIP_CHECK(hipStreamWaitEvent(c.s, join, 0));
+    FFP_CHECK(fgemm_sub(c, m - r1, n - n1, r1, A + r1 * lda, lda, A + n1, lda, A + r1 * lda + n1, lda));  // F, H
+    ev_put(fork);
+    ev_put(join);
+    ws.release(mk);
+    return FFP_OK;
 }
 
 int rows_perm(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, const int32_t *perm) {
@@ -495,7 +569,7 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
     }
     const Field &F = *c.F;
     if (leaf64_fits(m, n)) {
-        FFP_CHECK(leaf64_launch(F, m, n, A, lda, P, Q, c.rank_dev, s));
+        FFP_CHECK(leaf64_launch(F, m, n, A, lda, P, Q, c.rank_dev, nullptr, s));
         return read_rank(c.rank_dev, rank, s);
     }
     if (leaf_fits(m, n)) {
@@ -517,13 +591,7 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
     FFP_CHECK(rows_perm(c, m1, n - n1, A + n1, lda, P));
     FFP_CHECK(cols_perm(c, m - m1, n1, A + m1 * lda, lda, Q));
     // ---- 3. D = L1^-1 B1, E = C1 U1^-1, [F; H] -= [M1; E] D, G = C2 - E V1
-    int32_t *const L1U1 = A;
-    if (r1 > 0) {
-        FFP_CHECK(trsm_sub(c, 0, 0, 1, r1, n - n1, L1U1, lda, A + n1, lda));            // D
-        FFP_CHECK(trsm_sub(c, 1, 1, 0, m - m1, r1, L1U1, lda, A + m1 * lda, lda));     // E
-        FFP_CHECK(fgemm_sub(c, m - r1, n - n1, r1, A + r1 * lda, lda, A + n1, lda, A + r1 * lda + n1, lda));
-        FFP_CHECK(fgemm_sub(c, m - m1, n1 - r1, r1, A + m1 * lda, lda, A + r1, lda, A + m1 * lda + r1, lda));
-    }
+    FFP_CHECK(node_updates(c, m, n, m1, n1, r1, A, lda));
     // ---- 4. factor F (top-right remainder) and G (bottom-left remainder)
     const size_t mk = ws.mark();
     int32_t *P2 = (int32_t *)ws.take((size_t)(m1 - r1) * 4);
@@ -595,15 +663,53 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
 }
 }  // namespace
 
+// ---------------------------------------------------------------- generic speculation
+// When every leading minor of A is nonzero (generic rank profile) the rank
+// profile matrix is the diagonal, the quadrant order is the identity and the
+// recursion above reduces to LU without pivoting: every sub-block's rank is
+// min(rows, cols), every permutation and rotation is the identity, and no
+// rank has to be read back.  lu_generic runs exactly that recursion; leaves
+// raise *gflag on the first zero diagonal pivot (A is then not generic), in
+// which case the caller restores A and runs the general recursion.  The
+// result, when the flag stays clear, is bit-identical to the general one.
+static int lu_generic(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int *gflag) {
+    if (m == 0 || n == 0) return FFP_OK;
+    if (leaf64_fits(m, n)) return leaf64_launch(*c.F, m, n, A, lda, nullptr, nullptr, nullptr, gflag, c.s);
+    const int64_t m1 = m / 2, n1 = n / 2;
+    FFP_CHECK(lu_generic(c, m1, n1, A, lda, gflag));
+    const int64_t r1 = m1 < n1 ? m1 : n1;
+    FFP_CHECK(node_updates(c, m, n, m1, n1, r1, A, lda));
+    const int64_t fm = m1 - r1, fn = n - n1, gm = m - m1, gn = n1 - r1;
+    FFP_CHECK(lu_generic(c, fm, fn, A + r1 * lda + n1, lda, gflag));
+    FFP_CHECK(lu_generic(c, gm, gn, A + m1 * lda + r1, lda, gflag));
+    const int64_t r2 = fm < fn ? fm : fn, r3 = gm < gn ? gm : gn;
+    int32_t *const H = A + m1 * lda + n1;
+    if (r2 > 0) FFP_CHECK(trsm_sub(c, 1, 1, 0, m - m1, r2, A + r1 * lda + n1, lda, H, lda));
+    if (r3 > 0) {
+        FFP_CHECK(fgemm_sub(c, r3, n - n1 - r2, r2, H, lda, A + r1 * lda + n1 + r2, lda, H + r2, lda));
+        FFP_CHECK(trsm_sub(c, 0, 0, 1, r3, n - n1 - r2, A + m1 * lda + r1, lda, H + r2, lda));
+    }
+    int32_t *const R = H + r3 * lda + r2;
+    FFP_CHECK(fgemm_sub(c, m - m1 - r3, n - n1 - r2, r2, H + r3 * lda, lda, A + r1 * lda + n1 + r2, lda, R, lda));
+    FFP_CHECK(fgemm_sub(c, m - m1 - r3, n - n1 - r2, r3, A + (m1 + r3) * lda + r1, lda, H + r2, lda, R, lda));
+    return lu_generic(c, m - m1 - r3, n - n1 - r2, R, lda, gflag);
+}
+
+__global__ void k_set_int(int *dst, int v) { *dst = v; }
+
 size_t pluq_ws(int64_t m, int64_t n, const Field &F, int path) {
     // largest out-of-place permutation (the whole block) + index arrays along
-    // one root-to-leaf path + the rank word + limb planes of the largest product
+    // one root-to-leaf path + the rank word + limb planes of the largest
+    // product + the backup copy of A for the generic speculation
     int64_t depth = 2;
     for (int64_t x = (m > n ? m : n); x > 1; x >>= 1) ++depth;
     size_t b = (size_t)m * (size_t)n * 4 + 256;
     b += (size_t)depth * ((size_t)(m + n) * 4 * 3 + 4 * 256);
     b += 512;
-    if (path == FFP_PATH_INT8) b += fgemm_i8_ws(F, m, n, (m < n ? m : n));
+    if (path == FFP_PATH_INT8 || path == FFP_PATH_AUTO) b += fgemm_i8_ws(F, m, n, (m < n ? m : n));
+    b += (size_t)m * (size_t)n * 4 + 512;
+    // coefficients of the triangular solves' diagonal blocks
+    b += (size_t)(((m < n ? m : n) + 63) / 64) * (64 * 64 + 64) * 8 + 1024;
     return b;
 }
 
@@ -612,6 +718,34 @@ int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t
     int64_t *rank_dev = (int64_t *)ws.take(256);
     if (!rank_dev) return FFP_E_WORKSPACE;
     Ctx c{path, &F, &ws, s, rank_dev};
+    if (m > 64 && n > 64 && !getenv("FFP_PLUQ_GENERAL_ONLY")) {
+        // speculate that A has generic rank profile (keep a copy to fall back)
+        const size_t mk = ws.mark();
+        int32_t *backup = (int32_t *)ws.take((size_t)m * (size_t)n * 4);
+        int *gflag = (int *)rank_dev + 4;
+        if (!backup) return FFP_E_WORKSPACE;
+        FFP_CHECK(copy2d(m, n, A, lda, backup, n, s));
+        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, gflag, 0);
+        FFP_HIP_CHECK(hipGetLastError());
+        FFP_CHECK(lu_generic(c, m, n, A, lda, gflag));
+        int64_t flag = 0;
+        {
+            std::lock_guard<std::mutex> g(g_pin_mu);
+            if (!g_pin) FFP_HIP_CHECK(hipHostMalloc((void **)&g_pin, 64, hipHostMallocDefault));
+            FFP_HIP_CHECK(hipMemcpyAsync(g_pin, gflag, sizeof(int), hipMemcpyDeviceToHost, s));
+            FFP_HIP_CHECK(hipStreamSynchronize(s));
+            flag = *(int *)g_pin;
+        }
+        if (flag == 0) {
+            FFP_CHECK(iota(P, m, s));
+            FFP_CHECK(iota(Q, n, s));
+            *r = m < n ? m : n;
+            ws.release(mk);
+            return FFP_OK;
+        }
+        FFP_CHECK(copy2d(m, n, backup, n, A, lda, s));
+        ws.release(mk);
+    }
     return pluq_rec(c, m, n, A, lda, P, Q, r);
 }
 

@@ -257,3 +257,19 @@ def test_pluq_checks_medium(lib, orc):
     res = lib.pluq(Ad, p)
     err = checks.full_check(A, host(Ad), host(res.P), host(res.Q), res.rank, p, orc.order, exact_limit=0)
     assert err is None, err
+
+
+def test_pluq_general_path_on_generic_inputs(lib, orc):
+    """Generic-rank-profile inputs normally take the speculative path; the
+    general recursion (FFP_PLUQ_GENERAL_ONLY=1) must give the same bits."""
+    import os
+    p = 65521
+    rng = np.random.default_rng(31)
+    for (m, n) in [(300, 300), (257, 129), (129, 400)]:
+        A = rng.integers(0, p, (m, n)).astype(np.int32)
+        os.environ["FFP_PLUQ_GENERAL_ONLY"] = "1"
+        try:
+            _pluq_compare(lib, orc, A, p, 0, "general-only")
+        finally:
+            del os.environ["FFP_PLUQ_GENERAL_ONLY"]
+        _pluq_compare(lib, orc, A, p, 0, "speculative")
