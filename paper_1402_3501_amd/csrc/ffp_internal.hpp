@@ -88,6 +88,8 @@ int resolve_path(int path, uint32_t p, int64_t m, int64_t n, int64_t k);
 int ftrsm_run(int path, const Field &F, int side, int uplo, int trans, int diag, int64_t m,
               int64_t n, uint32_t alpha, const int32_t *T, int64_t ldt, int32_t *B, int64_t ldb,
               Arena &ws, hipStream_t s);
+// workspace bytes of ftrsm_run (block inverses + products of the given path)
+size_t ftrsm_ws(int path, const Field &F, int side, int64_t m, int64_t n);
 
 // B <- alpha * B mod p
 int scale_mat(const Field &F, int64_t m, int64_t n, uint32_t alpha, int32_t *B, int64_t ldb,
@@ -118,8 +120,9 @@ int permute_inplace(int64_t m, int64_t n, int32_t *A, int64_t lda, const PermSpe
 int copy2d(int64_t m, int64_t n, const int32_t *src, int64_t lds, int32_t *dst, int64_t ldd,
            hipStream_t s);
 
-// single-wave PLUQ leaf for blocks of at most 64 x 64 (rank to rank_dev);
-// with gflag non-null: generic-only mode (see leaf64.hip)
+// PLUQ leaf for blocks of at most 64 x 64 (one wave; rank to rank_dev); with
+// gflag non-null: plain LU leaf of the generic-rank-profile attempt (four
+// waves; a zero pivot sets *gflag, P, Q and rank are not written)
 int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
                   int64_t *rank_dev, int *gflag, hipStream_t s);
 

@@ -1,189 +1,290 @@
 // ftrsm over Z/pZ: triangular solves, Section 2.1 (trsm).  As in the paper,
-// the solve is block recursive so that almost all of its work is fgemm; the
-// base case (triangles of at most kTB rows) runs in LDS with exact inverses
-// of the diagonal and one delayed reduction per solved component
-// (the R_trsm count of Section 3.1: one reduction for the dot product, one
-// for the division by a non-unit diagonal).
+// the solve is block recursive so that almost all of its work is fgemm.  The
+// base case differs from a substitution: the inverses of all diagonal 64 x 64
+// blocks are formed at once (one workgroup per block), and each base case is
+// then a 64 x 64 by 64 x nv product on the FP64 matrix cores, in place.  The
+// result is the same (arithmetic is exact); the chain of dependent steps of a
+// solve is one inversion launch plus one product per base block.
 #include "ffp_internal.hpp"
 #include "ffp_device.hpp"
 
 namespace ffp {
 
-constexpr int kTB = 64;   // base-case triangle size
-constexpr int kTV = 128;  // vectors per workgroup (one per thread)
+constexpr int kTB = 64;  // base-case triangle size
 
-// Solve, for each of nv independent vectors, x_i = (b_i - sum_{t before i} c(i,t) x_t) / diag_i
-// for i in processing order (ascending if FWD, else descending), where
-//   c(i,t) = swap ? T[t][i] : T[i][t]   and   diag_i = unit ? 1 : T[i][i].
-// Vector v, component i lives at B[i][v] (COLS) or B[v][i].
-// One thread per vector.  The coefficients sit in LDS in processing order
-// (zero padded to 64, read as broadcasts).  Components are solved in four
-// groups of 16 held in registers: a group first takes the contributions of
-// the solved groups (kept in LDS, one column per thread), then solves its
-// 16 x 16 diagonal block in registers.
-template <bool RED, bool FWD, bool COLS>
-__global__ __launch_bounds__(kTV) void k_trsm_base(int d, int64_t nv, const int32_t *__restrict__ T,
-                                                   int64_t ldt, int32_t *__restrict__ B, int64_t ldb,
-                                                   int swap, int unit, double p, double pinv, int32_t half,
-                                                   int kchunk) {
-    constexpr int G = 16;
-    __shared__ __attribute__((aligned(16))) double Ts[kTB][kTB];
-    __shared__ double Dinv[kTB];
-    __shared__ double Xs[kTB][kTV + 1];
+// centred residue of an integer-valued double |x| < 2^53
+__device__ __forceinline__ double cmod(double x, double p, double pinv, double half) {
+    const double c = mod_canon(x, p, pinv);
+    return c > half ? c - p : c;
+}
+
+// One doubling step on SZ x SZ diagonal blocks: for each pair,
+// Ts = M21 W11, then W21 = -W22 Ts.  W11 and W22 are lower triangular with
+// zeros stored above the diagonal, so the dot products run over all SZ terms
+// (fixed trip counts, fully unrolled); a thread takes 32 SZ / 256 outputs.
+template <int SZ, bool RED>
+__device__ __forceinline__ void inv_level(const int32_t (*Ms)[kTB + 1], double (*Ws)[kTB + 1], double *Ts,
+                                          double p, double pinv, double hd, int kchunk) {
+    constexpr int N2 = SZ * SZ, TOT = (kTB / 2) * SZ, PER = TOT < 256 ? 1 : TOT / 256;
     const int tid = threadIdx.x;
-    const int32_t ip = (int32_t)p;
-
-    {
-        // issue all coefficient loads before any use (out-of-triangle and
-        // padding entries read T[0][0] and are zeroed afterwards)
-        constexpr int PER = kTB * kTB / kTV;
-        int32_t cv[PER];
+    if (tid < TOT) {
+        double acc[PER];
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = tid + q * kTV, a = e / kTB, b = e % kTB;
-            const bool in = b < a && a < d;
-            const int i = in ? (FWD ? a : d - 1 - a) : 0, t = in ? (FWD ? b : d - 1 - b) : 0;
-            cv[q] = swap ? T[(int64_t)t * ldt + i] : T[(int64_t)i * ldt + t];
+        for (int e = 0; e < PER; ++e) acc[e] = 0.0;
+#pragma unroll
+        for (int t = 0; t < SZ; ++t) {
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                const int idx = tid + e * 256, q = idx / N2, i = (idx / SZ) % SZ, j = idx % SZ, r0 = 2 * SZ * q;
+                acc[e] = fma((double)Ms[r0 + SZ + i][r0 + t], Ws[r0 + t][r0 + j], acc[e]);
+            }
+            if (RED && (t + 1) % kchunk == 0) {
+#pragma unroll
+                for (int e = 0; e < PER; ++e) acc[e] = mod_near(acc[e], p, pinv);
+            }
         }
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int e = tid + q * kTV, a = e / kTB, b = e % kTB;
-            Ts[a][b] = (b < a && a < d) ? centre(cv[q], p, half) : 0.0;
-        }
-    }
-    for (int a = tid; a < kTB; a += kTV) {
-        double dv = 1.0;
-        if (a < d && !unit) {
-            const int i = FWD ? a : d - 1 - a;
-            dv = (double)inv_mod(T[(int64_t)i * ldt + i], ip);
-        }
-        Dinv[a] = dv;
+        for (int e = 0; e < PER; ++e) Ts[tid + e * 256] = cmod(acc[e], p, pinv, hd);
     }
     __syncthreads();
-    const int64_t v = (int64_t)blockIdx.x * kTV + tid;
-    if (v >= nv) return;
-    int32_t *base = COLS ? B + v : B + v * ldb;
-    const int64_t step = COLS ? ldb : 1;
-    const int ngroups = (d + G - 1) / G;
-#pragma unroll 1
-    for (int J = 0; J < ngroups; ++J) {
-        const int a0 = J * G;
-        double bj[G], acc[G], xg[G];
+    if (tid < TOT) {
+        double acc[PER];
 #pragma unroll
-        for (int j = 0; j < G; ++j) {
-            const int a = a0 + j;
-            const int i = a < d ? (FWD ? a : d - 1 - a) : 0;
-            bj[j] = (double)base[i * step];
-            acc[j] = 0.0;
-        }
-        // contributions of the groups already solved
-#pragma unroll 1
-        for (int I = 0; I < J; ++I) {
+        for (int e = 0; e < PER; ++e) acc[e] = 0.0;
 #pragma unroll
-            for (int t = 0; t < G; ++t) {
-                const double xt = Xs[I * G + t][tid];
+        for (int t = 0; t < SZ; ++t) {
 #pragma unroll
-                for (int j = 0; j < G; ++j) acc[j] = fma(Ts[a0 + j][I * G + t], xt, acc[j]);
-                if (RED && ((t + 1) % kchunk == 0)) {
-#pragma unroll
-                    for (int j = 0; j < G; ++j) acc[j] = mod_near(acc[j], p, pinv);
-                }
+            for (int e = 0; e < PER; ++e) {
+                const int idx = tid + e * 256, q = idx / N2, i = (idx / SZ) % SZ, j = idx % SZ, r0 = 2 * SZ * q;
+                acc[e] = fma(Ws[r0 + SZ + i][r0 + SZ + t], Ts[q * N2 + t * SZ + j], acc[e]);
             }
-            if (RED) {
+            if (RED && (t + 1) % kchunk == 0) {
 #pragma unroll
-                for (int j = 0; j < G; ++j) acc[j] = mod_near(acc[j], p, pinv);
+                for (int e = 0; e < PER; ++e) acc[e] = mod_near(acc[e], p, pinv);
             }
         }
-        // diagonal block
 #pragma unroll
-        for (int j = 0; j < G; ++j) {
-            double sdiag = 0.0;
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * 256, q = idx / N2, i = (idx / SZ) % SZ, j = idx % SZ, r0 = 2 * SZ * q;
+            Ws[r0 + SZ + i][r0 + j] = cmod(-acc[e], p, pinv, hd);
+        }
+    }
+    __syncthreads();
+}
+
+// Inverses of the diagonal 64 x 64 blocks of op(T), one workgroup per block.
+// The stored triangle is read as a lower triangular Lm (transposed when the
+// upper triangle is stored; rows and columns past the end are identity
+// padding) and inverted by doubling: the 1 x 1 blocks are the inverses of
+// the diagonal, and the inverse of [M11 0; M21 M22] is
+// [W11 0; -W22 (M21 W11), W22] for s x s blocks, s = 1, 2, .., 32.  Every
+// dot product has at most 32 terms of centred residues and is exact (or
+// reduced every kchunk terms when p is large).  The terms of Ts = M21 W11
+// with t < j and of W22 Ts with t > i are zero and are summed anyway.  op(T)^-1 is Lm^-1 when op(T)
+// is lower triangular and its transpose otherwise; it is stored as 64 x 64
+// centred doubles, zero outside the block.
+template <bool RED>
+__global__ __launch_bounds__(256) void k_trsm_inv(int64_t d, const int32_t *__restrict__ T, int64_t ldt,
+                                                  int upper_stored, int unit, int eff_lower,
+                                                  double *__restrict__ Winv, double p, double pinv,
+                                                  int32_t half, int kchunk) {
+    __shared__ int32_t Ms[kTB][kTB + 1];
+    __shared__ double Ws[kTB][kTB + 1];
+    __shared__ double Ts[kTB * kTB / 4];
+    const int tid = threadIdx.x;
+    const int64_t o = (int64_t)blockIdx.x * kTB;
+    const int db = (int)(d - o < kTB ? d - o : kTB);
+    const double hd = (double)half;
+    {
+        constexpr int PER = kTB * kTB / 256;
+        int32_t v[PER];
 #pragma unroll
-            for (int t = 0; t < j; ++t) {
-                sdiag = fma(Ts[a0 + j][a0 + t], xg[t], sdiag);
-                if (RED && ((t + 1) % kchunk == 0)) sdiag = mod_near(sdiag, p, pinv);
-            }
-            double sj = bj[j] - mod_near(acc[j], p, pinv);
-            sj = mod_canon(sj - sdiag, p, pinv);
-            const double xa = mod_canon(sj * Dinv[a0 + j], p, pinv);
-            bj[j] = xa;
-            xg[j] = xa > (double)half ? xa - p : xa;
+        for (int e = 0; e < PER; ++e) {
+            // coalesced along the stored row: (a, b) = (stored row, stored column)
+            const int idx = tid + e * 256, a = idx / kTB, b = idx % kTB;
+            const bool in = a < db && b < db && (upper_stored ? b > a : b < a);
+            v[e] = in ? T[(o + a) * ldt + o + b] : 0;
         }
 #pragma unroll
-        for (int j = 0; j < G; ++j) {
-            Xs[a0 + j][tid] = xg[j];
-            const int a = a0 + j;
-            if (a < d) base[(FWD ? a : d - 1 - a) * step] = (int32_t)bj[j];
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * 256, a = idx / kTB, b = idx % kTB;
+            const int32_t c = v[e] > half ? v[e] - (int32_t)p : v[e];
+            if (upper_stored) Ms[b][a] = c;
+            else Ms[a][b] = c;
         }
+    }
+    for (int idx = tid; idx < kTB * kTB; idx += 256) Ws[idx / kTB][idx % kTB] = 0.0;
+    __syncthreads();
+    if (tid < kTB) {
+        double w = 1.0;
+        if (tid < db && !unit) {
+            const int32_t t = T[(o + tid) * ldt + o + tid];
+            const int32_t ip = (int32_t)p;
+            w = (double)(p < 16777216.0 ? inv_mod_small(t, ip) : inv_mod(t, ip));
+            if (w > hd) w -= p;
+        }
+        Ws[tid][tid] = w;
+    }
+    __syncthreads();
+    inv_level<1, RED>(Ms, Ws, Ts, p, pinv, hd, kchunk);
+    inv_level<2, RED>(Ms, Ws, Ts, p, pinv, hd, kchunk);
+    inv_level<4, RED>(Ms, Ws, Ts, p, pinv, hd, kchunk);
+    inv_level<8, RED>(Ms, Ws, Ts, p, pinv, hd, kchunk);
+    inv_level<16, RED>(Ms, Ws, Ts, p, pinv, hd, kchunk);
+    inv_level<32, RED>(Ms, Ws, Ts, p, pinv, hd, kchunk);
+    double *out = Winv + (int64_t)blockIdx.x * kTB * kTB;
+    for (int idx = tid; idx < kTB * kTB; idx += 256) {
+        const int i = idx / kTB, j = idx % kTB;
+        out[idx] = (i < db && j < db) ? (eff_lower ? Ws[i][j] : Ws[j][i]) : 0.0;
     }
 }
 
-static int trsm_base(const Field &F, int d, int64_t nv, const int32_t *T, int64_t ldt, int32_t *B,
-                     int64_t ldb, bool fwd, bool swap, bool unit, bool cols_are_vectors, hipStream_t s) {
-    if (d <= 0 || nv <= 0) return FFP_OK;
-    // exact while 2p + (terms per sum) * half^2 < 2^53: a sum takes at most 48
-    // terms unreduced, else is reduced every kchunk of its terms
-    const bool red = F.kexact < 48;
-    const int kchunk = (int)(F.kexact < 1 ? 1 : (F.kexact > kTB ? kTB : F.kexact));
-    dim3 grid((unsigned)((nv + kTV - 1) / kTV));
-#define FFP_TB(R_, F_, C_)                                                                                    \
-    hipLaunchKernelGGL((k_trsm_base<R_, F_, C_>), grid, dim3(kTV), 0, s, d, nv, T, ldt, B, ldb, (int)swap, \
-                       (int)unit, F.pd, F.pinv, (int32_t)F.half, kchunk)
-#define FFP_TB2(R_)                                  \
-    if (fwd) {                                       \
-        if (cols_are_vectors) FFP_TB(R_, true, true); \
-        else FFP_TB(R_, true, false);                \
-    } else {                                         \
-        if (cols_are_vectors) FFP_TB(R_, false, true); \
-        else FFP_TB(R_, false, false);               \
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Base case: X = W B_b (left: B_b is db rows x nv vectors) or X = B_b W
+// (right: nv vector rows x db), in place, with W the block inverse.  One
+// workgroup per 64 vectors: the 64 x 64 slab is read whole into LDS, then
+// multiplied on the FP64 matrix cores (4 waves, 32 x 32 each) and written
+// back; slabs of different workgroups are disjoint.
+template <bool LEFT, bool RED>
+__global__ __launch_bounds__(256) void k_trsm_apply(int db, int64_t nv, const double *__restrict__ W,
+                                                    int32_t *__restrict__ B, int64_t ldb, double p, double pinv,
+                                                    int32_t half, int ksteps) {
+    __shared__ double Ws[kTB][kTB + 2];
+    __shared__ int32_t Ss[kTB][kTB + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t v0 = (int64_t)blockIdx.x * kTB;
+    {
+        constexpr int PER = kTB * kTB / 256;
+        double w[PER];
+        int32_t b[PER];
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * 256, a = idx / kTB, c = idx % kTB;
+            w[e] = W[idx];
+            // LEFT: slab element (component a, vector c); right: (vector a, component c)
+            const bool in = LEFT ? (a < db && v0 + c < nv) : (v0 + a < nv && c < db);
+            b[e] = in ? (LEFT ? B[a * ldb + v0 + c] : B[(v0 + a) * ldb + c]) : 0;
+        }
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * 256, a = idx / kTB, c = idx % kTB;
+            Ws[a][c] = w[e];
+            Ss[a][c] = b[e] > half ? b[e] - (int32_t)p : b[e];
+        }
     }
-    if (red) { FFP_TB2(true) } else { FFP_TB2(false) }
-#undef FFP_TB2
-#undef FFP_TB
+    __syncthreads();
+    const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
+    v4d acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int nks = (db + 3) / 4;
+    int steps = 0;
+    for (int ks = 0; ks < nks; ++ks) {
+        const int kr = ks * 4 + (lane >> 4);
+        double a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int r = wm0 + i * 16 + (lane & 15);
+            a[i] = LEFT ? Ws[r][kr] : (double)Ss[r][kr];
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int c = wn0 + j * 16 + (lane & 15);
+            b[j] = LEFT ? (double)Ss[kr][c] : Ws[kr][c];
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (RED && ++steps == ksteps) {
+            steps = 0;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[i][j][v] = mod_near(acc[i][j][v], p, pinv);
+        }
+    }
+    // lane l holds rows l/16 + 4v of column l%16 of each 16 x 16 block
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = wm0 + i * 16 + (lane >> 4) + 4 * v, c = wn0 + j * 16 + (lane & 15);
+                const int32_t x = (int32_t)mod_canon(acc[i][j][v], p, pinv);
+                if (LEFT) {
+                    if (r < db && v0 + c < nv) B[r * ldb + v0 + c] = x;
+                } else {
+                    if (v0 + r < nv && c < db) B[(v0 + r) * ldb + c] = x;
+                }
+            }
+}
+
+static int trsm_apply(const Field &F, int side, int db, int64_t nv, const double *W, int32_t *B, int64_t ldb,
+                      hipStream_t s) {
+    if (db <= 0 || nv <= 0) return FFP_OK;
+    // a k-step adds 4 products; exact while 2p + terms * half^2 < 2^53
+    const bool red = F.kexact < db;
+    const int ksteps = (int)(F.kexact / 4 < 1 ? 1 : (F.kexact / 4 > 16 ? 16 : F.kexact / 4));
+    dim3 grid((unsigned)((nv + kTB - 1) / kTB));
+#define FFP_TA(L_, R_)                                                                                    \
+    hipLaunchKernelGGL((k_trsm_apply<L_, R_>), grid, dim3(256), 0, s, db, nv, W, B, ldb, F.pd, F.pinv, \
+                       (int32_t)F.half, ksteps)
+    if (side == 0) {
+        if (red) FFP_TA(true, true);
+        else FFP_TA(true, false);
+    } else {
+        if (red) FFP_TA(false, true);
+        else FFP_TA(false, false);
+    }
+#undef FFP_TA
     FFP_HIP_CHECK(hipGetLastError());
     return FFP_OK;
 }
 
-// op(T) = trans ? T^T : T.  eff_lower: op(T) is lower triangular.
-static int trsm_rec(int path, const Field &F, int side, bool eff_lower, int trans, bool unit, int64_t d,
-                    int64_t nv, const int32_t *T, int64_t ldt, int32_t *B, int64_t ldb, Arena &ws,
+// op(T) = trans ? T^T : T.  eff_lower: op(T) is lower triangular.  Split
+// points are multiples of 64 from the origin of the top-level triangle, so
+// every base case is one of its diagonal blocks, whose inverse is W.
+static int trsm_rec(int path, const Field &F, int side, bool eff_lower, int trans, int64_t d, int64_t nv,
+                    const int32_t *T, int64_t ldt, int32_t *B, int64_t ldb, const double *W, Arena &ws,
                     hipStream_t s) {
     if (d <= 0 || nv <= 0) return FFP_OK;
     const uint32_t minus1 = F.p - 1;
-    if (d <= kTB) {
-        // left: x_i uses op(T)[i][t]; right: x_j uses op(T)[t][j]
-        const bool fwd = side == 0 ? eff_lower : !eff_lower;
-        const bool swap = (side == 1) != (trans != 0);
-        return trsm_base(F, (int)d, nv, T, ldt, B, ldb, fwd, swap, unit, side == 0, s);
-    }
-    int64_t d1 = ((d / 2 + kTB - 1) / kTB) * kTB;
-    if (d1 >= d) d1 = d / 2;
+    if (d <= kTB) return trsm_apply(F, side, (int)d, nv, W, B, ldb, s);
+    const int64_t d1 = ((d / 2 + kTB - 1) / kTB) * kTB;  // < d for d > 64
     const int64_t d2 = d - d1;
     const int32_t *T11 = T, *T22 = T + d1 * ldt + d1;
+    const double *W1 = W, *W2 = W + (d1 / kTB) * kTB * kTB;
     // op(T)21 (d2 x d1) and op(T)12 (d1 x d2) as (pointer, transposed?) of the stored T
     const int32_t *op21 = trans ? T + d1 : T + d1 * ldt;   // trans: (T[0:d1, d1:d])^T
     const int32_t *op12 = trans ? T + d1 * ldt : T + d1;   // trans: (T[d1:d, 0:d1])^T
     if (side == 0) {
         int32_t *B1 = B, *B2 = B + d1 * ldb;
         if (eff_lower) {
-            FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, unit, d1, nv, T11, ldt, B1, ldb, ws, s));
+            FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, d1, nv, T11, ldt, B1, ldb, W1, ws, s));
             FFP_CHECK(fgemm_any(path, F, trans, 0, d2, nv, d1, minus1, op21, ldt, B1, ldb, 1, B2, ldb, ws, s));
-            FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, unit, d2, nv, T22, ldt, B2, ldb, ws, s));
+            FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, d2, nv, T22, ldt, B2, ldb, W2, ws, s));
         } else {
-            FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, unit, d2, nv, T22, ldt, B2, ldb, ws, s));
+            FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, d2, nv, T22, ldt, B2, ldb, W2, ws, s));
             FFP_CHECK(fgemm_any(path, F, trans, 0, d1, nv, d2, minus1, op12, ldt, B2, ldb, 1, B1, ldb, ws, s));
-            FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, unit, d1, nv, T11, ldt, B1, ldb, ws, s));
+            FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, d1, nv, T11, ldt, B1, ldb, W1, ws, s));
         }
     } else {
         int32_t *B1 = B, *B2 = B + d1;
         if (!eff_lower) {
-            FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, unit, d1, nv, T11, ldt, B1, ldb, ws, s));
+            FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, d1, nv, T11, ldt, B1, ldb, W1, ws, s));
             FFP_CHECK(fgemm_any(path, F, 0, trans, nv, d2, d1, minus1, B1, ldb, op12, ldt, 1, B2, ldb, ws, s));
-            FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, unit, d2, nv, T22, ldt, B2, ldb, ws, s));
+            FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, d2, nv, T22, ldt, B2, ldb, W2, ws, s));
         } else {
-            FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, unit, d2, nv, T22, ldt, B2, ldb, ws, s));
+            FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, d2, nv, T22, ldt, B2, ldb, W2, ws, s));
             FFP_CHECK(fgemm_any(path, F, 0, trans, nv, d1, d2, minus1, B2, ldb, op21, ldt, 1, B1, ldb, ws, s));
-            FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, unit, d1, nv, T11, ldt, B1, ldb, ws, s));
+            FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, d1, nv, T11, ldt, B1, ldb, W1, ws, s));
         }
     }
     return FFP_OK;
@@ -193,15 +294,39 @@ int ftrsm_run(int path, const Field &F, int side, int uplo, int trans, int diag,
               uint32_t alpha, const int32_t *T, int64_t ldt, int32_t *B, int64_t ldb, Arena &ws,
               hipStream_t s) {
     if (m <= 0 || n <= 0) return FFP_OK;
-    if (!ws.counting) FFP_CHECK(scale_mat(F, m, n, alpha, B, ldb, s));
     const bool eff_lower = (uplo == 0) != (trans != 0);
     const int64_t d = side == 0 ? m : n, nv = side == 0 ? n : m;
+    const int64_t nblk = (d + kTB - 1) / kTB;
+    const size_t mk = ws.mark();
+    double *W = (double *)ws.take((size_t)nblk * kTB * kTB * sizeof(double));
     if (ws.counting) {
         // the recursion's products on the INT8 path need limb workspace for at most d/2 x max(d, nv)
         if (path == FFP_PATH_INT8) ws.take(fgemm_i8_ws(F, d, nv > d ? nv : d, d));
+        ws.release(mk);
         return FFP_OK;
     }
-    return trsm_rec(path, F, side, eff_lower, trans, diag != 0, d, nv, T, ldt, B, ldb, ws, s);
+    if (!W) return FFP_E_WORKSPACE;
+    FFP_CHECK(scale_mat(F, m, n, alpha, B, ldb, s));
+    // dot products of the inversion take at most 32 terms
+    const bool red = F.kexact < 32;
+    const int kchunk = (int)(F.kexact < 1 ? 1 : (F.kexact > 32 ? 32 : F.kexact));
+#define FFP_TI(R_)                                                                                          \
+    hipLaunchKernelGGL((k_trsm_inv<R_>), dim3((unsigned)nblk), dim3(256), 0, s, d, T, ldt, uplo, diag, \
+                       (int)eff_lower, W, F.pd, F.pinv, (int32_t)F.half, kchunk)
+    if (red) FFP_TI(true);
+    else FFP_TI(false);
+#undef FFP_TI
+    FFP_HIP_CHECK(hipGetLastError());
+    FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, d, nv, T, ldt, B, ldb, W, ws, s));
+    ws.release(mk);
+    return FFP_OK;
+}
+
+size_t ftrsm_ws(int path, const Field &F, int side, int64_t m, int64_t n) {
+    Arena a;
+    a.counting = true;
+    ftrsm_run(path, F, side, 0, 0, 0, m, n, 1, nullptr, 1, nullptr, 1, a, nullptr);
+    return a.peak;
 }
 
 }  // namespace ffp

@@ -40,16 +40,11 @@ __device__ __forceinline__ uint64_t first_k64(uint64_t x, int k) {
 
 enum { B_NONE = 0, B_ROW = 1, B_COL = 2 };
 
-// GEN: generic-only mode used by the speculative factorisation: a zero
-// diagonal pivot sets *gflag and leaves the block untouched; nothing runs once
-// *gflag is set; P, Q and the rank are not written (they are the identity and
-// min(mb, nb)).
-template <bool RED, bool SMALLP, bool GEN>
+template <bool RED, bool SMALLP>
 __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restrict__ A, int64_t lda,
                                               int32_t *__restrict__ P, int32_t *__restrict__ Q,
                                               int64_t *__restrict__ rank_out, double p, double pinv, int32_t half,
-                                              int64_t kexact, int *__restrict__ gflag) {
-    if (GEN && __builtin_amdgcn_readfirstlane(*(volatile int *)gflag) != 0) return;
+                                              int64_t kexact) {
     __shared__ double W[64][65];
     __shared__ double Lc[64];
     __shared__ int rord[64], cord[64];
@@ -124,12 +119,6 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
             }
         }
         __syncthreads();
-    }
-    if (GEN) {
-        if (!generic) {
-            if (threadIdx.x == 0) *gflag = 1;
-            return;
-        }
     }
     if (generic) {
         r = kd;
@@ -275,29 +264,141 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
     if (lane < nb) {
         const int cp = cord[lane];
         for (int i = 0; i < mb; ++i) A[(int64_t)rord[i] * lda + cp] = (int32_t)mod_canon(W[i][lane], p, pinv);
-        if (!GEN) Q[cp] = lane;
+        Q[cp] = lane;
     }
-    if (!GEN) {
-        if (lane < mb) P[rord[lane]] = lane;
-        if (lane == 0) *rank_out = r;
+    if (lane < mb) P[rord[lane]] = lane;
+    if (lane == 0) *rank_out = r;
+}
+
+// Leaf of the generic-rank-profile factorisation (plain LU: pivots (k, k)),
+// fraction free: step k multiplies each remaining row by the pivot instead of
+// dividing the pivot row by it,
+//   W[i][c] <- q_k W[i][c] - W[i][k] W[k][c]   (i, c > k),   q_k = W[k][k],
+// so the steps need no inverse.  Row i then holds s_i times the row of the
+// ordinary elimination, s_k = q_0 ... q_{k-1}, hence (all exact mod p)
+//   L[i][k] = W[i][k] / q_k   and   U[k][c] = W[k][c] / s_k,
+// and all 64 inverses (one per lane) and the prefix products s_k^-1 are
+// formed once at the end.  A pivot is zero exactly when the ordinary one is.
+// NW waves; lane c owns column c and wave w owns rows w, w + NW, ..., held in
+// registers, so the updates stay balanced as the active block shrinks.  Per
+// step the owner of row k publishes it through LDS (double buffered, one
+// barrier), and each wave reads its multipliers W[i][k] from lane k.
+// Entries are brought back to |W| <= (p-1)/2 + 3 every step (rounded
+// quotient), so q W - a u stays below 2^53 for every p the FP64 embedding
+// takes, and a pivot is zero mod p exactly when it is 0.0.  SMALLP selects
+// the inverse routine.  A zero pivot sets *gflag and leaves A untouched (A is
+// written only at the end); nothing runs once *gflag is set.
+template <bool SMALLP, int NW>
+__global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *__restrict__ A, int64_t lda,
+                                                      double p, double pinv, int32_t half, int *__restrict__ gflag) {
+    constexpr int RPW = 64 / NW;  // rows per wave
+    if (__builtin_amdgcn_readfirstlane(*(volatile int *)gflag) != 0) return;
+    __shared__ double rowbuf[2][64];
+    __shared__ double qv[64], QI[64], SI[64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const double hd = (double)half;
+    double R[RPW];
+    {
+        int32_t av[RPW];
+        const int cl = lane < nb ? lane : 0;
+#pragma unroll
+        for (int e = 0; e < RPW; ++e) {
+            const int i = wave + NW * e;
+            av[e] = A[(int64_t)(i < mb ? i : 0) * lda + cl];
+        }
+#pragma unroll
+        for (int e = 0; e < RPW; ++e) {
+            const int i = wave + NW * e;
+            R[e] = (i < mb && lane < nb) ? centre(av[e], p, half) : 0.0;
+        }
+    }
+    const int kd = mb < nb ? mb : nb;
+#pragma unroll
+    for (int kk = 0; kk < RPW; ++kk) {
+        // steps k = kk NW + w: row k is row kk of wave w
+        for (int w = 0; w < NW; ++w) {
+            const int k = kk * NW + w;
+            if (k >= kd) break;
+            if (wave == w) rowbuf[k & 1][lane] = R[kk];
+            __syncthreads();
+            const double u = rowbuf[k & 1][lane];
+            const double q = rld(u, k);
+            if (q == 0.0) {
+                // every wave sees the same pivot and leaves here
+                if (tid == 0) *gflag = 1;
+                return;
+            }
+            if (tid == 0) qv[k] = q;
+            const bool cact = lane > k && lane < nb;
+#pragma unroll
+            for (int e = kk; e < RPW; ++e) {
+                // rows below k: all of rows kk+1.. of each wave, row kk of the waves after w
+                if (e == kk && wave <= w) continue;
+                const int i = wave + NW * e;
+                const double a = rld(R[e], k);
+                const double t = mod_near(fma(-a, u, q * R[e]), p, pinv);
+                R[e] = (i < mb && cact) ? t : R[e];
+            }
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        // q_t^-1 per lane, then exclusive prefix products s_t^-1 = q_0^-1 ... q_{t-1}^-1
+        double qi = 1.0;
+        if (lane < kd) {
+            double qc = qv[lane];  // |qc| < p
+            if (qc < 0.0) qc += p;
+            qi = SMALLP ? (double)inv_mod_small((int32_t)qc, (int32_t)p) : (double)inv_mod((int32_t)qc, (int32_t)p);
+            if (qi > hd) qi -= p;
+        }
+        double sc = qi;  // inclusive scan
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double o = __shfl_up(sc, off);
+            if (lane >= off) {
+                const double c = mod_canon(sc * o, p, pinv);
+                sc = c > hd ? c - p : c;
+            }
+        }
+        double sx = __shfl_up(sc, 1);
+        if (lane == 0) sx = 1.0;
+        QI[lane] = qi;
+        SI[lane] = sx;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < RPW; ++e) {
+        const int i = wave + NW * e;
+        const int lim = i < kd ? i : kd;
+        const double f = lane < lim ? QI[lane] : SI[i];
+        if (i < mb && lane < nb) A[(int64_t)i * lda + lane] = (int32_t)mod_canon(R[e] * f, p, pinv);
     }
 }
+
+constexpr int kGenWaves = 8;
 
 int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
                   int64_t *rank_dev, int *gflag, hipStream_t s) {
     const bool red = F.kexact < 64;
     const bool small = F.p < (1u << 24);
-#define FFP_L64(R_, S_, G_)                                                                                      \
-    hipLaunchKernelGGL((k_leaf64<R_, S_, G_>), dim3(1), dim3(64), 0, s, (int)m, (int)n, A, lda, P, Q, rank_dev, \
-                       F.pd, F.pinv, (int32_t)F.half, F.kexact, gflag)
-#define FFP_L64G(G_)                                                       \
-    if (red) {                                                             \
-        if (small) FFP_L64(true, true, G_); else FFP_L64(true, false, G_); \
-    } else {                                                               \
-        if (small) FFP_L64(false, true, G_); else FFP_L64(false, false, G_); \
+#define FFP_L64(R_, S_)                                                                                    \
+    hipLaunchKernelGGL((k_leaf64<R_, S_>), dim3(1), dim3(64), 0, s, (int)m, (int)n, A, lda, P, Q, rank_dev, \
+                       F.pd, F.pinv, (int32_t)F.half, F.kexact)
+#define FFP_SEL(X_)                                     \
+    if (red) {                                          \
+        if (small) X_(true, true); else X_(true, false); \
+    } else {                                            \
+        if (small) X_(false, true); else X_(false, false); \
     }
-    if (gflag) { FFP_L64G(true) } else { FFP_L64G(false) }
-#undef FFP_L64G
+    if (gflag) {
+        if (small) hipLaunchKernelGGL((k_leaf_gen<true, kGenWaves>), dim3(1), dim3(64 * kGenWaves), 0, s, (int)m, (int)n, A,
+                                      lda, F.pd, F.pinv, (int32_t)F.half, gflag);
+        else hipLaunchKernelGGL((k_leaf_gen<false, kGenWaves>), dim3(1), dim3(64 * kGenWaves), 0, s, (int)m, (int)n, A,
+                                lda, F.pd, F.pinv, (int32_t)F.half, gflag);
+    } else {
+        FFP_SEL(FFP_L64)
+    }
+#undef FFP_SEL
 #undef FFP_L64
     FFP_HIP_CHECK(hipGetLastError());
     return FFP_OK;

@@ -499,18 +499,18 @@ int node_updates(Ctx &c, int64_t m, int64_t n, int64_t m1, int64_t n1, int64_t r
     hipStream_t s2;
     FFP_CHECK(side_stream(&s2));
     // workspace of the side stream, reserved until the join
-    size_t need = 0;
-    if (c.path != FFP_PATH_FP64 && F.limbs > 0) {
-        const size_t a = fgemm_i8_ws(F, m - m1, r1, r1), b = fgemm_i8_ws(F, m - m1, n1 - r1, r1);
-        need = (a > b ? a : b) + 1024;
+    const bool i8 = c.path != FFP_PATH_FP64 && F.limbs > 0;
+    size_t need = ftrsm_ws(i8 ? FFP_PATH_INT8 : FFP_PATH_FP64, F, 1, m - m1, r1);
+    if (i8) {
+        const size_t b = fgemm_i8_ws(F, m - m1, n1 - r1, r1);
+        need = need > b ? need : b;
     }
+    need += 1024;
     const size_t mk = ws.mark();
     Arena a2;
-    if (need) {
-        a2.base = (char *)ws.take(need);
-        a2.cap = need;
-        if (!a2.base) return FFP_E_WORKSPACE;
-    }
+    a2.base = (char *)ws.take(need);
+    a2.cap = need;
+    if (!a2.base) return FFP_E_WORKSPACE;
     hipEvent_t fork, join;
     FFP_CHECK(ev_get(&fork));
     FFP_CHECK(ev_get(&join));
@@ -708,8 +708,8 @@ size_t pluq_ws(int64_t m, int64_t n, const Field &F, int path) {
     b += 512;
     if (path == FFP_PATH_INT8 || path == FFP_PATH_AUTO) b += fgemm_i8_ws(F, m, n, (m < n ? m : n));
     b += (size_t)m * (size_t)n * 4 + 512;
-    // coefficients of the triangular solves' diagonal blocks
-    b += (size_t)(((m < n ? m : n) + 63) / 64) * (64 * 64 + 64) * 8 + 1024;
+    // inverses of the triangular solves' diagonal blocks (two solves at once)
+    b += 2 * ((size_t)(((m < n ? m : n) + 63) / 64) + 2) * 64 * 64 * 8 + 4096;
     return b;
 }
 
