@@ -21,6 +21,9 @@ SOURCES = ["core.hip", "fgemm_f64.hip", "fgemm_i8.hip", "ftrsm.hip", "pluq.hip",
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # FP64 matrix-core accumulators in ordinary VGPRs: otherwise every loop
+    # iteration copies them into the accumulation registers and back
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

@@ -75,6 +75,7 @@ const char *ffp_error_string(int code) {
         case FFP_E_RANGE: return "input entry outside [0, p)";
         case FFP_E_UNSUPPORTED: return "unsupported request";
         case FFP_E_NODEVICE: return "no usable gfx950 device";
+        case FFP_E_INTERNAL: return "internal error: a device-side wait gave up";
         default: return code < 0 && code > -64 ? "invalid argument" : "unknown error";
     }
 }

@@ -90,6 +90,11 @@ int ftrsm_run(int path, const Field &F, int side, int uplo, int trans, int diag,
               Arena &ws, hipStream_t s);
 // workspace bytes of ftrsm_run (block inverses + products of the given path)
 size_t ftrsm_ws(int path, const Field &F, int side, int64_t m, int64_t n);
+// solve with the inverses of the diagonal 64 x 64 blocks of op(T) = T already
+// formed (W: ceil(d / 64) blocks of 64 x 64 centred doubles); alpha = 1
+int ftrsm_with_inverses(int path, const Field &F, int side, bool lower, int64_t m, int64_t n,
+                        const int32_t *T, int64_t ldt, int32_t *B, int64_t ldb, const double *W, Arena &ws,
+                        hipStream_t s);
 
 // B <- alpha * B mod p
 int scale_mat(const Field &F, int64_t m, int64_t n, uint32_t alpha, int32_t *B, int64_t ldb,
@@ -121,10 +126,11 @@ int copy2d(int64_t m, int64_t n, const int32_t *src, int64_t lds, int32_t *dst, 
            hipStream_t s);
 
 // PLUQ leaf for blocks of at most 64 x 64 (one wave; rank to rank_dev); with
-// gflag non-null: plain LU leaf of the generic-rank-profile attempt (four
-// waves; a zero pivot sets *gflag, P, Q and rank are not written)
+// gflag non-null: plain LU leaf of the generic-rank-profile attempt (a zero
+// pivot sets *gflag; P, Q and rank are not written; with Linv / Uinv
+// non-null, the 64 x 64 inverses of its L and U blocks are stored there)
 int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
-                  int64_t *rank_dev, int *gflag, hipStream_t s);
+                  int64_t *rank_dev, int *gflag, double *Linv, double *Uinv, hipStream_t s);
 
 // PLUQ (host recursion); P, Q device outputs (local indices); returns rank via *r
 int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P,

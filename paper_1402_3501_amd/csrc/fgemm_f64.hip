@@ -160,6 +160,275 @@ __global__ __launch_bounds__(256) void k_fgemm_f64(int64_t m, int64_t n, int64_t
     }
 }
 
+// Small and medium products (up to a few hundred 64 x 64 output tiles): the
+// same arithmetic with K staged 64 at a time, so a product with k <= 64 makes
+// a single round trip to memory for its operands (the C tile for beta != 0
+// is fetched alongside), and longer K overlaps the next 64-slice with the
+// current one.  Operands sit in LDS as centred int32 (converted to FP64 as
+// the matrix-core fragments are read).
+template <bool TA, bool TB, bool RED>
+__global__ __launch_bounds__(256) void k_fgemm_f64_k64(int64_t m, int64_t n, int64_t k,
+                                                       const int32_t *__restrict__ A, int64_t lda,
+                                                       const int32_t *__restrict__ B, int64_t ldb,
+                                                       int32_t *__restrict__ C, int64_t ldc, double p, double pinv,
+                                                       int32_t half, double alpha, double beta, int kchunk_steps) {
+    constexpr int T = 64;
+    __shared__ int32_t As[2][T][T + 1];  // [kk][i]
+    __shared__ int32_t Bs[2][T][T + 1];  // [kk][j]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
+    const int64_t m0 = (int64_t)blockIdx.y * T, n0 = (int64_t)blockIdx.x * T;
+    const int32_t ip = (int32_t)p;
+    int32_t ra[16], rb[16];
+    // loads are unconditional (addresses clamped into the operand) so that
+    // they are all in flight together; out-of-range elements are zeroed after
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int idx = tid + e * 256, x = idx % T, y = idx / T;  // x along the contiguous dimension
+            {
+                const int i = TA ? x : y, kk = TA ? y : x;
+                const int64_t gi = m0 + i, gk = k0 + kk;
+                const int64_t ci = gi < m ? gi : m - 1, ck = gk < k ? gk : k - 1;
+                ra[e] = TA ? A[ck * lda + ci] : A[ci * lda + ck];
+            }
+            {
+                const int j = TB ? y : x, kk = TB ? x : y;
+                const int64_t gj = n0 + j, gk = k0 + kk;
+                const int64_t cj = gj < n ? gj : n - 1, ck = gk < k ? gk : k - 1;
+                rb[e] = TB ? B[cj * ldb + ck] : B[ck * ldb + cj];
+            }
+        }
+    };
+    auto mask = [&](int64_t k0) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int idx = tid + e * 256, x = idx % T, y = idx / T;
+            {
+                const int i = TA ? x : y, kk = TA ? y : x;
+                if (!(m0 + i < m && k0 + kk < k)) ra[e] = 0;
+            }
+            {
+                const int j = TB ? y : x, kk = TB ? x : y;
+                if (!(n0 + j < n && k0 + kk < k)) rb[e] = 0;
+            }
+        }
+    };
+    auto store = [&](int buf, int64_t k0) {
+        mask(k0);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int idx = tid + e * 256, x = idx % T, y = idx / T;
+            As[buf][TA ? y : x][TA ? x : y] = ra[e] > half ? ra[e] - ip : ra[e];
+            Bs[buf][TB ? x : y][TB ? y : x] = rb[e] > half ? rb[e] - ip : rb[e];
+        }
+    };
+    // C tile prefetch (beta != 0); lane l holds rows l/16 + 4v of column l%16
+    int32_t cpre[2][2][4];
+    if (beta != 0.0) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t gi = m0 + wm0 + i * 16 + (lane >> 4) + 4 * v, gj = n0 + wn0 + j * 16 + (lane & 15);
+                    cpre[i][j][v] = C[(gi < m ? gi : m - 1) * ldc + (gj < n ? gj : n - 1)];
+                }
+    }
+    v4d acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int64_t nt = (k + T - 1) / T;
+    int steps = 0;
+    if (nt > 0) {
+        load(0);
+        store(0, 0);
+    }
+    __syncthreads();
+    for (int64_t t = 0; t < nt; ++t) {
+        const int buf = (int)(t & 1);
+        if (t + 1 < nt) load((t + 1) * T);
+#pragma unroll
+        for (int ks = 0; ks < T / 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            double a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = (double)As[buf][kr][wm0 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) b[j] = (double)Bs[buf][kr][wn0 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+            if (RED && ++steps == kchunk_steps) {
+                steps = 0;
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[i][j][v] = mod_near(acc[i][j][v], p, pinv);
+            }
+        }
+        if (t + 1 < nt) store(buf ^ 1, (t + 1) * T);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t gi = m0 + wm0 + i * 16 + (lane >> 4) + 4 * v, gj = n0 + wn0 + j * 16 + (lane & 15);
+                if (gi < m && gj < n) {
+                    double r = mod_canon(acc[i][j][v], p, pinv);
+                    if (alpha != 1.0) r = mod_canon(alpha * r, p, pinv);
+                    if (beta != 0.0) {
+                        double c = (double)cpre[i][j][v];
+                        if (beta != 1.0) c = mod_canon(beta * c, p, pinv);
+                        r += c;
+                        if (r >= p) r -= p;
+                    }
+                    C[gi * ldc + gj] = (int32_t)r;
+                }
+            }
+}
+
+// Small products: one wave per 32 x 32 output tile, so that a product of a
+// few 64 x 64 blocks is spread over many compute units instead of running
+// as one long workgroup.  K is staged 32 at a time (the next slice is loaded
+// while the current one is multiplied); loads are unconditional with
+// clamped 32-bit indices; for the common alpha = +-1, beta in {0, 1} the
+// epilogue is a single reduction of +-acc + C.
+template <bool TA, bool TB, bool RED>
+__global__ __launch_bounds__(64) void k_fgemm_f64_t32(int m, int n, int k, const int32_t *__restrict__ A,
+                                                      uint32_t lda, const int32_t *__restrict__ B, uint32_t ldb,
+                                                      int32_t *__restrict__ C, uint32_t ldc, double p, double pinv,
+                                                      int32_t half, double alpha, double beta, int kchunk_steps) {
+    constexpr int T = 32;
+    __shared__ int32_t As[2][T][T + 1];  // [kk][i]
+    __shared__ int32_t Bs[2][T][T + 1];  // [kk][j]
+    const int lane = threadIdx.x;
+    const int m0 = blockIdx.y * T, n0 = blockIdx.x * T;
+    const int32_t ip = (int32_t)p;
+    const int x = lane & 31, y0 = lane >> 5;  // element (x along the contiguous dimension, y0 + 2e)
+    int32_t ra[16], rb[16];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int y = y0 + 2 * e;
+            {
+                const int i = TA ? x : y, kk = TA ? y : x;
+                const int ci = min(m0 + i, m - 1), ck = min(k0 + kk, k - 1);
+                ra[e] = TA ? A[(uint64_t)ck * lda + ci] : A[(uint64_t)ci * lda + ck];
+            }
+            {
+                const int j = TB ? y : x, kk = TB ? x : y;
+                const int cj = min(n0 + j, n - 1), ck = min(k0 + kk, k - 1);
+                rb[e] = TB ? B[(uint64_t)cj * ldb + ck] : B[(uint64_t)ck * ldb + cj];
+            }
+        }
+    };
+    auto store = [&](int buf, int k0) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int y = y0 + 2 * e;
+            {
+                const int i = TA ? x : y, kk = TA ? y : x;
+                const int32_t v = (m0 + i < m && k0 + kk < k) ? ra[e] : 0;
+                As[buf][kk][i] = v > half ? v - ip : v;
+            }
+            {
+                const int j = TB ? y : x, kk = TB ? x : y;
+                const int32_t v = (n0 + j < n && k0 + kk < k) ? rb[e] : 0;
+                Bs[buf][kk][j] = v > half ? v - ip : v;
+            }
+        }
+    };
+    int32_t cpre[2][2][4];
+    if (beta != 0.0) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int gi = min(m0 + i * 16 + (lane >> 4) + 4 * v, m - 1), gj = min(n0 + j * 16 + (lane & 15), n - 1);
+                    cpre[i][j][v] = C[(uint64_t)gi * ldc + gj];
+                }
+    }
+    v4d acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    const int nt = (k + T - 1) / T;
+    int steps = 0;
+    if (nt > 0) {
+        load(0);
+        store(0, 0);
+    }
+    __syncthreads();
+    for (int t = 0; t < nt; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < nt) load((t + 1) * T);
+#pragma unroll
+        for (int ks = 0; ks < T / 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            double a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = (double)As[buf][kr][i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) b[j] = (double)Bs[buf][kr][j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+            if (RED && ++steps == kchunk_steps) {
+                steps = 0;
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[i][j][v] = mod_near(acc[i][j][v], p, pinv);
+            }
+        }
+        if (t + 1 < nt) store(buf ^ 1, (t + 1) * T);
+        __syncthreads();
+    }
+    // +-1 and beta in {0, 1}: one reduction of sign * acc + C (exact: |acc| < 2^53 - p)
+    const double sgn = alpha == 1.0 ? 1.0 : (alpha == p - 1.0 ? -1.0 : 0.0);
+    const bool fast = sgn != 0.0 && (beta == 0.0 || beta == 1.0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gi = m0 + i * 16 + (lane >> 4) + 4 * v, gj = n0 + j * 16 + (lane & 15);
+                double r;
+                if (fast) {
+                    r = mod_canon(fma(sgn, acc[i][j][v], beta != 0.0 ? (double)cpre[i][j][v] : 0.0), p, pinv);
+                } else {
+                    r = mod_canon(acc[i][j][v], p, pinv);
+                    if (alpha != 1.0) r = mod_canon(alpha * r, p, pinv);
+                    if (beta != 0.0) {
+                        double c = (double)cpre[i][j][v];
+                        if (beta != 1.0) c = mod_canon(beta * c, p, pinv);
+                        r += c;
+                        if (r >= p) r -= p;
+                    }
+                }
+                if (gi < m && gj < n) C[(uint64_t)gi * ldc + gj] = (int32_t)r;
+            }
+}
+
 template <int BM, int BN, bool RED>
 static void launch_tiles(int ta, int tb, dim3 grid, hipStream_t s, int64_t m, int64_t n, int64_t k,
                          const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, int32_t *C,
@@ -189,10 +458,33 @@ int fgemm_f64(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, u
         dim3 grid((unsigned)((n + 127) / 128), (unsigned)((m + 127) / 128));
         if (red) launch_tiles<128, 128, true>(ta, tb, grid, s, m, n, k, A, lda, B, ldb, C, ldc, p, pinv, half, a, b, ksteps);
         else launch_tiles<128, 128, false>(ta, tb, grid, s, m, n, k, A, lda, B, ldb, C, ldc, p, pinv, half, a, b, ksteps);
+    } else if (((m + 63) / 64) * ((n + 63) / 64) < 256 && m < (1ll << 30) && n < (1ll << 30) && k < (1ll << 30) &&
+               lda < (1ll << 31) && ldb < (1ll << 31) && ldc < (1ll << 31)) {
+        dim3 grid((unsigned)((n + 31) / 32), (unsigned)((m + 31) / 32));
+#define FFP_T32(TA_, TB_, R_)                                                                               \
+    hipLaunchKernelGGL((k_fgemm_f64_t32<TA_, TB_, R_>), grid, dim3(64), 0, s, (int)m, (int)n, (int)k, A,    \
+                       (uint32_t)lda, B, (uint32_t)ldb, C, (uint32_t)ldc, p, pinv, half, a, b, ksteps)
+#define FFP_T32R(R_)                                          \
+    if (!ta && !tb) FFP_T32(false, false, R_);                 \
+    else if (ta && !tb) FFP_T32(true, false, R_);              \
+    else if (!ta && tb) FFP_T32(false, true, R_);              \
+    else FFP_T32(true, true, R_);
+        if (red) { FFP_T32R(true) } else { FFP_T32R(false) }
+#undef FFP_T32R
+#undef FFP_T32
     } else {
         dim3 grid((unsigned)((n + 63) / 64), (unsigned)((m + 63) / 64));
-        if (red) launch_tiles<64, 64, true>(ta, tb, grid, s, m, n, k, A, lda, B, ldb, C, ldc, p, pinv, half, a, b, ksteps);
-        else launch_tiles<64, 64, false>(ta, tb, grid, s, m, n, k, A, lda, B, ldb, C, ldc, p, pinv, half, a, b, ksteps);
+#define FFP_K64(TA_, TB_, R_)                                                                                  \
+    hipLaunchKernelGGL((k_fgemm_f64_k64<TA_, TB_, R_>), grid, dim3(256), 0, s, m, n, k, A, lda, B, ldb, C, ldc, \
+                       p, pinv, half, a, b, ksteps)
+#define FFP_K64R(R_)                                          \
+    if (!ta && !tb) FFP_K64(false, false, R_);                 \
+    else if (ta && !tb) FFP_K64(true, false, R_);              \
+    else if (!ta && tb) FFP_K64(false, true, R_);              \
+    else FFP_K64(true, true, R_);
+        if (red) { FFP_K64R(true) } else { FFP_K64R(false) }
+#undef FFP_K64R
+#undef FFP_K64
     }
     FFP_HIP_CHECK(hipGetLastError());
     return FFP_OK;

@@ -35,26 +35,46 @@ static inline int64_t rup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // zero outside rows < R, kk < K.  Tile 64 x 64 through LDS so that both the
 // read (along the stored contiguous dimension) and the write (along kk) are
 // coalesced.
+// one operand to split: rows of length K (row stride sr, element stride sk)
+struct SplitSrc {
+    const int32_t *X;
+    int64_t sr, sk, R, plane;
+    int8_t *dst;
+};
+
+// Both operands of a product in one launch: row tiles [0, rtA) are A's, the
+// rest B's.
 template <int L>
-__global__ __launch_bounds__(256) void k_split(const int32_t *__restrict__ X, int64_t sr, int64_t sk, int64_t R,
-                                               int64_t K, int64_t Kp, int64_t plane, int8_t *__restrict__ dst,
+__global__ __launch_bounds__(256) void k_split(SplitSrc sa, SplitSrc sb, int64_t rtA, int64_t K, int64_t Kp,
                                                int32_t half, int32_t p) {
+    const bool isb = (int64_t)blockIdx.y >= rtA;
+    const int32_t *__restrict__ X = isb ? sb.X : sa.X;
+    const int64_t sr = isb ? sb.sr : sa.sr, sk = isb ? sb.sk : sa.sk, R = isb ? sb.R : sa.R;
+    const int64_t plane = isb ? sb.plane : sa.plane;
+    int8_t *__restrict__ dst = isb ? sb.dst : sa.dst;
     __shared__ int32_t tile[64][65];
     const int tid = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.y * 64, k0 = (int64_t)blockIdx.x * 64;
+    const int64_t r0 = ((int64_t)blockIdx.y - (isb ? rtA : 0)) * 64, k0 = (int64_t)blockIdx.x * 64;
     const bool along_k = sk == 1;
+    // unconditional loads (addresses clamped into the operand) so that all 16
+    // are in flight together; out-of-range elements are zeroed afterwards
+    int32_t v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int idx = tid + e * 256;
         const int a = idx & 63, b = idx >> 6;   // a runs along the contiguous source dimension
         const int rr = along_k ? b : a, kk = along_k ? a : b;
         const int64_t gr = r0 + rr, gk = k0 + kk;
-        int32_t v = 0;
-        if (gr < R && gk < K) {
-            v = X[gr * sr + gk * sk];
-            v = v > half ? v - p : v;  // centred
-        }
-        tile[rr][kk] = v;
+        v[e] = X[(gr < R ? gr : R - 1) * sr + (gk < K ? gk : K - 1) * sk];
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int idx = tid + e * 256;
+        const int a = idx & 63, b = idx >> 6;
+        const int rr = along_k ? b : a, kk = along_k ? a : b;
+        const bool in = r0 + rr < R && k0 + kk < K;
+        const int32_t c = v[e] > half ? v[e] - p : v[e];  // centred
+        tile[rr][kk] = in ? c : 0;
     }
     __syncthreads();
     // 64 rows x 16 words (4 digits of consecutive kk per word) per digit plane
@@ -239,10 +259,9 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
         const int32_t *Bb = tb ? B + kc0 : B + kc0 * ldb;
         const int64_t asr = ta ? 1 : lda, ask = ta ? lda : 1;
         const int64_t bsr = tb ? ldb : 1, bsk = tb ? 1 : ldb;
-        hipLaunchKernelGGL((k_split<L>), dim3((unsigned)(Kp / 64), (unsigned)(Mp / 64)), dim3(256), 0, s, Ab, asr,
-                           ask, m, kc, Kp, planeA, Ad, (int32_t)F.half, (int32_t)F.p);
-        hipLaunchKernelGGL((k_split<L>), dim3((unsigned)(Kp / 64), (unsigned)(Np / 64)), dim3(256), 0, s, Bb, bsr,
-                           bsk, n, kc, Kp, planeB, Bd, (int32_t)F.half, (int32_t)F.p);
+        const SplitSrc sa{Ab, asr, ask, m, planeA, Ad}, sb{Bb, bsr, bsk, n, planeB, Bd};
+        hipLaunchKernelGGL((k_split<L>), dim3((unsigned)(Kp / 64), (unsigned)((Mp + Np) / 64)), dim3(256), 0, s, sa,
+                           sb, Mp / 64, kc, Kp, (int32_t)F.half, (int32_t)F.p);
         const double be = kc0 == 0 ? (double)beta : 1.0;
         {
             ProfScope prof(FFP_PATH_INT8, 2.0 * (double)m * (double)n * (double)kc, s);

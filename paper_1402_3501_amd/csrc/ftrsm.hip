@@ -7,70 +7,11 @@
 // solve is one inversion launch plus one product per base block.
 #include "ffp_internal.hpp"
 #include "ffp_device.hpp"
+#include "trinv.hpp"
 
 namespace ffp {
 
 constexpr int kTB = 64;  // base-case triangle size
-
-// centred residue of an integer-valued double |x| < 2^53
-__device__ __forceinline__ double cmod(double x, double p, double pinv, double half) {
-    const double c = mod_canon(x, p, pinv);
-    return c > half ? c - p : c;
-}
-
-// One doubling step on SZ x SZ diagonal blocks: for each pair,
-// Ts = M21 W11, then W21 = -W22 Ts.  W11 and W22 are lower triangular with
-// zeros stored above the diagonal, so the dot products run over all SZ terms
-// (fixed trip counts, fully unrolled); a thread takes 32 SZ / 256 outputs.
-template <int SZ, bool RED>
-__device__ __forceinline__ void inv_level(const int32_t (*Ms)[kTB + 1], double (*Ws)[kTB + 1], double *Ts,
-                                          double p, double pinv, double hd, int kchunk) {
-    constexpr int N2 = SZ * SZ, TOT = (kTB / 2) * SZ, PER = TOT < 256 ? 1 : TOT / 256;
-    const int tid = threadIdx.x;
-    if (tid < TOT) {
-        double acc[PER];
-#pragma unroll
-        for (int e = 0; e < PER; ++e) acc[e] = 0.0;
-#pragma unroll
-        for (int t = 0; t < SZ; ++t) {
-#pragma unroll
-            for (int e = 0; e < PER; ++e) {
-                const int idx = tid + e * 256, q = idx / N2, i = (idx / SZ) % SZ, j = idx % SZ, r0 = 2 * SZ * q;
-                acc[e] = fma((double)Ms[r0 + SZ + i][r0 + t], Ws[r0 + t][r0 + j], acc[e]);
-            }
-            if (RED && (t + 1) % kchunk == 0) {
-#pragma unroll
-                for (int e = 0; e < PER; ++e) acc[e] = mod_near(acc[e], p, pinv);
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < PER; ++e) Ts[tid + e * 256] = cmod(acc[e], p, pinv, hd);
-    }
-    __syncthreads();
-    if (tid < TOT) {
-        double acc[PER];
-#pragma unroll
-        for (int e = 0; e < PER; ++e) acc[e] = 0.0;
-#pragma unroll
-        for (int t = 0; t < SZ; ++t) {
-#pragma unroll
-            for (int e = 0; e < PER; ++e) {
-                const int idx = tid + e * 256, q = idx / N2, i = (idx / SZ) % SZ, j = idx % SZ, r0 = 2 * SZ * q;
-                acc[e] = fma(Ws[r0 + SZ + i][r0 + SZ + t], Ts[q * N2 + t * SZ + j], acc[e]);
-            }
-            if (RED && (t + 1) % kchunk == 0) {
-#pragma unroll
-                for (int e = 0; e < PER; ++e) acc[e] = mod_near(acc[e], p, pinv);
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int idx = tid + e * 256, q = idx / N2, i = (idx / SZ) % SZ, j = idx % SZ, r0 = 2 * SZ * q;
-            Ws[r0 + SZ + i][r0 + j] = cmod(-acc[e], p, pinv, hd);
-        }
-    }
-    __syncthreads();
-}
 
 // Inverses of the diagonal 64 x 64 blocks of op(T), one workgroup per block.
 // The stored triangle is read as a lower triangular Lm (transposed when the
@@ -101,13 +42,15 @@ __global__ __launch_bounds__(256) void k_trsm_inv(int64_t d, const int32_t *__re
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             // coalesced along the stored row: (a, b) = (stored row, stored column)
+            // unconditional (clamped) loads, all in flight together
             const int idx = tid + e * 256, a = idx / kTB, b = idx % kTB;
-            const bool in = a < db && b < db && (upper_stored ? b > a : b < a);
-            v[e] = in ? T[(o + a) * ldt + o + b] : 0;
+            v[e] = T[(o + (a < db ? a : db - 1)) * ldt + o + (b < db ? b : db - 1)];
         }
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * 256, a = idx / kTB, b = idx % kTB;
+            const bool in = a < db && b < db && (upper_stored ? b > a : b < a);
+            if (!in) v[e] = 0;
             const int32_t c = v[e] > half ? v[e] - (int32_t)p : v[e];
             if (upper_stored) Ms[b][a] = c;
             else Ms[a][b] = c;
@@ -126,12 +69,7 @@ __global__ __launch_bounds__(256) void k_trsm_inv(int64_t d, const int32_t *__re
         Ws[tid][tid] = w;
     }
     __syncthreads();
-    inv_level<1, RED>(Ms, Ws, Ts, p, pinv, hd, kchunk);
-    inv_level<2, RED>(Ms, Ws, Ts, p, pinv, hd, kchunk);
-    inv_level<4, RED>(Ms, Ws, Ts, p, pinv, hd, kchunk);
-    inv_level<8, RED>(Ms, Ws, Ts, p, pinv, hd, kchunk);
-    inv_level<16, RED>(Ms, Ws, Ts, p, pinv, hd, kchunk);
-    inv_level<32, RED>(Ms, Ws, Ts, p, pinv, hd, kchunk);
+    tri_inverse_levels<RED>(tid, Ms, Ws, Ts, p, pinv, hd, kchunk);
     double *out = Winv + (int64_t)blockIdx.x * kTB * kTB;
     for (int idx = tid; idx < kTB * kTB; idx += 256) {
         const int i = idx / kTB, j = idx % kTB;
@@ -162,13 +100,17 @@ __global__ __launch_bounds__(256) void k_trsm_apply(int db, int64_t nv, const do
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * 256, a = idx / kTB, c = idx % kTB;
             w[e] = W[idx];
-            // LEFT: slab element (component a, vector c); right: (vector a, component c)
-            const bool in = LEFT ? (a < db && v0 + c < nv) : (v0 + a < nv && c < db);
-            b[e] = in ? (LEFT ? B[a * ldb + v0 + c] : B[(v0 + a) * ldb + c]) : 0;
+            // LEFT: slab element (component a, vector c); right: (vector a, component c);
+            // unconditional (clamped) loads, zeroed below when out of range
+            const int ac = LEFT ? (a < db ? a : db - 1) : (v0 + a < nv ? a : (int)(nv - 1 - v0));
+            const int cc = LEFT ? (v0 + c < nv ? c : (int)(nv - 1 - v0)) : (c < db ? c : db - 1);
+            b[e] = LEFT ? B[ac * ldb + v0 + cc] : B[(v0 + ac) * ldb + cc];
         }
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * 256, a = idx / kTB, c = idx % kTB;
+            const bool in = LEFT ? (a < db && v0 + c < nv) : (v0 + a < nv && c < db);
+            if (!in) b[e] = 0;
             Ws[a][c] = w[e];
             Ss[a][c] = b[e] > half ? b[e] - (int32_t)p : b[e];
         }
@@ -320,6 +262,14 @@ int ftrsm_run(int path, const Field &F, int side, int uplo, int trans, int diag,
     FFP_CHECK(trsm_rec(path, F, side, eff_lower, trans, d, nv, T, ldt, B, ldb, W, ws, s));
     ws.release(mk);
     return FFP_OK;
+}
+
+int ftrsm_with_inverses(int path, const Field &F, int side, bool lower, int64_t m, int64_t n,
+                        const int32_t *T, int64_t ldt, int32_t *B, int64_t ldb, const double *W, Arena &ws,
+                        hipStream_t s) {
+    if (m <= 0 || n <= 0) return FFP_OK;
+    const int64_t d = side == 0 ? m : n, nv = side == 0 ? n : m;
+    return trsm_rec(path, F, side, lower, 0, d, nv, T, ldt, B, ldb, W, ws, s);
 }
 
 size_t ftrsm_ws(int path, const Field &F, int side, int64_t m, int64_t n) {

@@ -13,6 +13,7 @@
 // Euclid on the pivot.
 #include "ffp_internal.hpp"
 #include "ffp_device.hpp"
+#include "trinv.hpp"
 
 namespace ffp {
 
@@ -279,22 +280,42 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
 //   L[i][k] = W[i][k] / q_k   and   U[k][c] = W[k][c] / s_k,
 // and all 64 inverses (one per lane) and the prefix products s_k^-1 are
 // formed once at the end.  A pivot is zero exactly when the ordinary one is.
+//
 // NW waves; lane c owns column c and wave w owns rows w, w + NW, ..., held in
 // registers, so the updates stay balanced as the active block shrinks.  Per
 // step the owner of row k publishes it through LDS (double buffered, one
-// barrier), and each wave reads its multipliers W[i][k] from lane k.
+// barrier); each wave first reads all its multipliers W[i][k] from lane k,
+// then runs the row updates side by side.
 // Entries are brought back to |W| <= (p-1)/2 + 3 every step (rounded
 // quotient), so q W - a u stays below 2^53 for every p the FP64 embedding
 // takes, and a pivot is zero mod p exactly when it is 0.0.  SMALLP selects
 // the inverse routine.  A zero pivot sets *gflag and leaves A untouched (A is
 // written only at the end); nothing runs once *gflag is set.
+// With Linv / Uinv non-null the leaf also stores L^-1 and U^-1 of its k x k
+// diagonal block (k = min(mb, nb); 64 x 64 centred doubles, zero outside),
+// the base-case inverses of later triangular solves with these blocks.
 template <bool SMALLP, int NW>
 __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *__restrict__ A, int64_t lda,
-                                                      double p, double pinv, int32_t half, int *__restrict__ gflag) {
+                                                      double p, double pinv, int32_t half, int *__restrict__ gflag,
+                                                      double *__restrict__ Linv, double *__restrict__ Uinv,
+                                                      int inv_red, int kchunk) {
+    static_assert(NW == 8, "the inverse stage takes two groups of 256 threads");
     constexpr int RPW = 64 / NW;  // rows per wave
     if (__builtin_amdgcn_readfirstlane(*(volatile int *)gflag) != 0) return;
-    __shared__ double rowbuf[2][64];
-    __shared__ double qv[64], QI[64], SI[64];
+    // the pivot-row slots are dead once the elimination is over and share
+    // their space with the buffers of the inverse stage
+    // the pivot-row buffer is dead once the elimination is over and shares
+    // its space with the buffers of the inverse stage
+    struct InvBufs {
+        int32_t Ms[2][kTri][kTri + 1];  // [0] L (unit lower), [1] U^T (lower)
+        double Ws[2][kTri][kTri + 1];
+        double Ts[2][kTri * kTri / 4];
+    };
+    __shared__ union {
+        double rowbuf[2][64];
+        InvBufs v;
+    } sh;
+    __shared__ double qv[64], QI[64], SI[64], SQ[64];
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const double hd = (double)half;
     double R[RPW];
@@ -319,9 +340,9 @@ __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *_
         for (int w = 0; w < NW; ++w) {
             const int k = kk * NW + w;
             if (k >= kd) break;
-            if (wave == w) rowbuf[k & 1][lane] = R[kk];
+            if (wave == w) sh.rowbuf[k & 1][lane] = R[kk];
             __syncthreads();
-            const double u = rowbuf[k & 1][lane];
+            const double u = sh.rowbuf[k & 1][lane];
             const double q = rld(u, k);
             if (q == 0.0) {
                 // every wave sees the same pivot and leaves here
@@ -330,18 +351,30 @@ __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *_
             }
             if (tid == 0) qv[k] = q;
             const bool cact = lane > k && lane < nb;
+            // rows below k: rows kk+1.. of each wave, row kk of the waves after w;
+            // all multipliers first, so that the row updates are independent
+            double a[RPW];
+#pragma unroll
+            for (int e = kk; e < RPW; ++e) a[e] = rld(R[e], k);
 #pragma unroll
             for (int e = kk; e < RPW; ++e) {
-                // rows below k: all of rows kk+1.. of each wave, row kk of the waves after w
-                if (e == kk && wave <= w) continue;
                 const int i = wave + NW * e;
-                const double a = rld(R[e], k);
-                const double t = mod_near(fma(-a, u, q * R[e]), p, pinv);
-                R[e] = (i < mb && cact) ? t : R[e];
+                const bool below = e > kk || wave > w;  // uniform; computed either way
+                const double t = mod_near(fma(-a[e], u, q * R[e]), p, pinv);
+                R[e] = (below && i < mb && cact) ? t : R[e];
             }
         }
     }
     __syncthreads();
+    const bool want_inv = Linv != nullptr;
+    if (want_inv) {
+        for (int idx = tid; idx < kTri * (kTri + 1); idx += 64 * NW) {
+            (&sh.v.Ms[0][0][0])[idx] = 0;
+            (&sh.v.Ms[1][0][0])[idx] = 0;
+            (&sh.v.Ws[0][0][0])[idx] = 0.0;
+            (&sh.v.Ws[1][0][0])[idx] = 0.0;
+        }
+    }
     if (wave == 0) {
         // q_t^-1 per lane, then exclusive prefix products s_t^-1 = q_0^-1 ... q_{t-1}^-1
         double qi = 1.0;
@@ -351,19 +384,29 @@ __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *_
             qi = SMALLP ? (double)inv_mod_small((int32_t)qc, (int32_t)p) : (double)inv_mod((int32_t)qc, (int32_t)p);
             if (qi > hd) qi -= p;
         }
-        double sc = qi;  // inclusive scan
+        // inclusive scans of q^-1 and of q (the latter for U[t][t]^-1 = q_t^-1 s_t)
+        double sc = qi, sq = 1.0;
+        if (lane < kd) {
+            sq = qv[lane];
+            if (sq > hd) sq -= p;
+        }
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            const double o = __shfl_up(sc, off);
+            const double o = __shfl_up(sc, off), o2 = __shfl_up(sq, off);
             if (lane >= off) {
-                const double c = mod_canon(sc * o, p, pinv);
+                const double c = mod_canon(sc * o, p, pinv), c2 = mod_canon(sq * o2, p, pinv);
                 sc = c > hd ? c - p : c;
+                sq = c2 > hd ? c2 - p : c2;
             }
         }
-        double sx = __shfl_up(sc, 1);
-        if (lane == 0) sx = 1.0;
+        double sx = __shfl_up(sc, 1), sqx = __shfl_up(sq, 1);
+        if (lane == 0) {
+            sx = 1.0;
+            sqx = 1.0;
+        }
         QI[lane] = qi;
         SI[lane] = sx;
+        SQ[lane] = sqx;
     }
     __syncthreads();
 #pragma unroll
@@ -371,14 +414,46 @@ __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *_
         const int i = wave + NW * e;
         const int lim = i < kd ? i : kd;
         const double f = lane < lim ? QI[lane] : SI[i];
-        if (i < mb && lane < nb) A[(int64_t)i * lda + lane] = (int32_t)mod_canon(R[e] * f, p, pinv);
+        const double v = mod_canon(R[e] * f, p, pinv);
+        if (i < mb && lane < nb) A[(int64_t)i * lda + lane] = (int32_t)v;
+        if (want_inv) {
+            // the k x k blocks: L strictly below the diagonal, U^T likewise
+            const double cv = v > hd ? v - p : v;
+            if (i < kd && lane < kd) {
+                if (lane < i) sh.v.Ms[0][i][lane] = (int32_t)cv;
+                else if (lane > i) sh.v.Ms[1][lane][i] = (int32_t)cv;
+            }
+            if (lane == i) {
+                sh.v.Ws[0][i][i] = 1.0;
+                double ud = 1.0;  // U[i][i]^-1 = q_i^-1 s_i
+                if (i < kd) {
+                    const double c = mod_canon(QI[i] * SQ[i], p, pinv);
+                    ud = c > hd ? c - p : c;
+                }
+                sh.v.Ws[1][i][i] = ud;
+            }
+        }
+    }
+    if (!want_inv) return;
+    __syncthreads();
+    {
+        const int g = __builtin_amdgcn_readfirstlane(tid >> 8), t = tid & 255;
+        if (inv_red) tri_inverse_levels<true>(t, sh.v.Ms[g], sh.v.Ws[g], sh.v.Ts[g], p, pinv, hd, kchunk);
+        else tri_inverse_levels<false>(t, sh.v.Ms[g], sh.v.Ws[g], sh.v.Ts[g], p, pinv, hd, kchunk);
+    }
+    // L^-1 and U^-1 = ((U^T)^-1)^T, zero outside the k x k block
+    for (int idx = tid; idx < kTri * kTri; idx += 64 * NW) {
+        const int i = idx / kTri, j = idx % kTri;
+        const bool in = i < kd && j < kd;
+        Linv[idx] = in ? sh.v.Ws[0][i][j] : 0.0;
+        Uinv[idx] = in ? sh.v.Ws[1][j][i] : 0.0;
     }
 }
 
 constexpr int kGenWaves = 8;
 
 int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
-                  int64_t *rank_dev, int *gflag, hipStream_t s) {
+                  int64_t *rank_dev, int *gflag, double *Linv, double *Uinv, hipStream_t s) {
     const bool red = F.kexact < 64;
     const bool small = F.p < (1u << 24);
 #define FFP_L64(R_, S_)                                                                                    \
@@ -391,10 +466,13 @@ int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda,
         if (small) X_(false, true); else X_(false, false); \
     }
     if (gflag) {
+        // dot products of the block inversion take at most 32 terms
+        const int inv_red = F.kexact < 32;
+        const int kchunk = (int)(F.kexact < 1 ? 1 : (F.kexact > 32 ? 32 : F.kexact));
         if (small) hipLaunchKernelGGL((k_leaf_gen<true, kGenWaves>), dim3(1), dim3(64 * kGenWaves), 0, s, (int)m, (int)n, A,
-                                      lda, F.pd, F.pinv, (int32_t)F.half, gflag);
+                                      lda, F.pd, F.pinv, (int32_t)F.half, gflag, Linv, Uinv, inv_red, kchunk);
         else hipLaunchKernelGGL((k_leaf_gen<false, kGenWaves>), dim3(1), dim3(64 * kGenWaves), 0, s, (int)m, (int)n, A,
-                                lda, F.pd, F.pinv, (int32_t)F.half, gflag);
+                                lda, F.pd, F.pinv, (int32_t)F.half, gflag, Linv, Uinv, inv_red, kchunk);
     } else {
         FFP_SEL(FFP_L64)
     }

@@ -569,7 +569,7 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
     }
     const Field &F = *c.F;
     if (leaf64_fits(m, n)) {
-        FFP_CHECK(leaf64_launch(F, m, n, A, lda, P, Q, c.rank_dev, nullptr, s));
+        FFP_CHECK(leaf64_launch(F, m, n, A, lda, P, Q, c.rank_dev, nullptr, nullptr, nullptr, s));
         return read_rank(c.rank_dev, rank, s);
     }
     if (leaf_fits(m, n)) {
@@ -666,34 +666,64 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
 // ---------------------------------------------------------------- generic speculation
 // When every leading minor of A is nonzero (generic rank profile) the rank
 // profile matrix is the diagonal, the quadrant order is the identity and the
-// recursion above reduces to LU without pivoting: every sub-block's rank is
-// min(rows, cols), every permutation and rotation is the identity, and no
-// rank has to be read back.  lu_generic runs exactly that recursion; leaves
-// raise *gflag on the first zero diagonal pivot (A is then not generic), in
-// which case the caller restores A and runs the general recursion.  The
-// result, when the flag stays clear, is bit-identical to the general one.
-static int lu_generic(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int *gflag) {
-    if (m == 0 || n == 0) return FFP_OK;
-    if (leaf64_fits(m, n)) return leaf64_launch(*c.F, m, n, A, lda, nullptr, nullptr, nullptr, gflag, c.s);
-    const int64_t m1 = m / 2, n1 = n / 2;
-    FFP_CHECK(lu_generic(c, m1, n1, A, lda, gflag));
-    const int64_t r1 = m1 < n1 ? m1 : n1;
-    FFP_CHECK(node_updates(c, m, n, m1, n1, r1, A, lda));
-    const int64_t fm = m1 - r1, fn = n - n1, gm = m - m1, gn = n1 - r1;
-    FFP_CHECK(lu_generic(c, fm, fn, A + r1 * lda + n1, lda, gflag));
-    FFP_CHECK(lu_generic(c, gm, gn, A + m1 * lda + r1, lda, gflag));
-    const int64_t r2 = fm < fn ? fm : fn, r3 = gm < gn ? gm : gn;
-    int32_t *const H = A + m1 * lda + n1;
-    if (r2 > 0) FFP_CHECK(trsm_sub(c, 1, 1, 0, m - m1, r2, A + r1 * lda + n1, lda, H, lda));
-    if (r3 > 0) {
-        FFP_CHECK(fgemm_sub(c, r3, n - n1 - r2, r2, H, lda, A + r1 * lda + n1 + r2, lda, H + r2, lda));
-        FFP_CHECK(trsm_sub(c, 0, 0, 1, r3, n - n1 - r2, A + m1 * lda + r1, lda, H + r2, lda));
-    }
-    int32_t *const R = H + r3 * lda + r2;
-    FFP_CHECK(fgemm_sub(c, m - m1 - r3, n - n1 - r2, r2, H + r3 * lda, lda, A + r1 * lda + n1 + r2, lda, R, lda));
-    FFP_CHECK(fgemm_sub(c, m - m1 - r3, n - n1 - r2, r3, A + (m1 + r3) * lda + r1, lda, H + r2, lda, R, lda));
-    return lu_generic(c, m - m1 - r3, n - n1 - r2, R, lda, gflag);
+// PLUQ decomposition is the LU decomposition without pivoting, P = Q = I:
+// every permutation and rotation is the identity and no rank has to be read
+// back.  That decomposition is unique, so it may be computed with any block
+// split: lu_generic splits off a leading square block whose size is a
+// multiple of 64,
+//   [A1 B1; C1 A4] = [L1 0; E L3] [U1 D; 0 U3],
+//   D = L1^-1 B1,  E = C1 U1^-1,  L3 U3 = A4 - E D,
+// so that every diagonal leaf is an aligned 64 x 64 block.  Each leaf stores
+// the inverses of its L and U blocks, which are exactly the base-case
+// inverses of the later solves with L1 and U1.  Leaves raise *gflag on the
+// first zero pivot (A is then not generic), and the caller restores A and
+// runs the general recursion.  The result, when the flag stays clear, is
+// bit-identical to the general one.
+namespace {
+constexpr int64_t kBlk = 64 * 64;  // doubles per stored block inverse
+
+int node_updates_gen(Ctx &c, int64_t m, int64_t n, int64_t h, int32_t *A, int64_t lda, const double *Li,
+                     const double *Ui) {
+    const Field &F = *c.F;
+    Arena &ws = *c.ws;
+    hipStream_t s2;
+    FFP_CHECK(side_stream(&s2));
+    size_t need = 1024;
+    if (c.path != FFP_PATH_FP64 && F.limbs > 0) need += fgemm_i8_ws(F, h, (m - h) > h ? (m - h) : h, h);
+    const size_t mk = ws.mark();
+    Arena a2;
+    a2.base = (char *)ws.take(need);
+    a2.cap = need;
+    if (!a2.base) return FFP_E_WORKSPACE;
+    hipEvent_t fork, join;
+    FFP_CHECK(ev_get(&fork));
+    FFP_CHECK(ev_get(&join));
+    FFP_HIP_CHECK(hipEventRecord(fork, c.s));
+    FFP_HIP_CHECK(hipStreamWaitEvent(s2, fork, 0));
+    // E = C1 U1^-1 on the side stream, D = L1^-1 B1 on the main one
+    FFP_CHECK(ftrsm_with_inverses(c.path, F, 1, false, m - h, h, A, lda, A + h * lda, lda, Ui, a2, s2));
+    FFP_HIP_CHECK(hipEventRecord(join, s2));
+    FFP_CHECK(ftrsm_with_inverses(c.path, F, 0, true, h, n - h, A, lda, A + h, lda, Li, ws, c.s));
+    FFP_HIP_CHECK(hipStreamWaitEvent(c.s, join, 0));
+    FFP_CHECK(fgemm_sub(c, m - h, n - h, h, A + h * lda, lda, A + h, lda, A + h * lda + h, lda));  // A4 - E D
+    ev_put(fork);
+    ev_put(join);
+    ws.release(mk);
+    return FFP_OK;
 }
+
+// Li / Ui: block-inverse slots from this block's diagonal offset on
+int lu_generic(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int *gflag, double *Li, double *Ui) {
+    if (m == 0 || n == 0) return FFP_OK;
+    if (leaf64_fits(m, n)) return leaf64_launch(*c.F, m, n, A, lda, nullptr, nullptr, nullptr, gflag, Li, Ui, c.s);
+    const int64_t k = m < n ? m : n;
+    const int64_t h = k <= 64 ? k : 64 * ((k + 127) / 128);
+    FFP_CHECK(lu_generic(c, h, h, A, lda, gflag, Li, Ui));
+    FFP_CHECK(node_updates_gen(c, m, n, h, A, lda, Li, Ui));
+    const int64_t off = (h / 64) * kBlk;  // h is a multiple of 64 whenever the rest is non-empty
+    return lu_generic(c, m - h, n - h, A + h * lda + h, lda, gflag, Li + off, Ui + off);
+}
+}  // namespace
 
 __global__ void k_set_int(int *dst, int v) { *dst = v; }
 
@@ -708,8 +738,10 @@ size_t pluq_ws(int64_t m, int64_t n, const Field &F, int path) {
     b += 512;
     if (path == FFP_PATH_INT8 || path == FFP_PATH_AUTO) b += fgemm_i8_ws(F, m, n, (m < n ? m : n));
     b += (size_t)m * (size_t)n * 4 + 512;
-    // inverses of the triangular solves' diagonal blocks (two solves at once)
+    // inverses of the triangular solves' diagonal blocks (two solves at once),
+    // and the leaves' L and U block inverses of the generic attempt
     b += 2 * ((size_t)(((m < n ? m : n) + 63) / 64) + 2) * 64 * 64 * 8 + 4096;
+    b += 2 * ((size_t)(((m < n ? m : n) + 63) / 64)) * 64 * 64 * 8 + 1024;
     return b;
 }
 
@@ -722,12 +754,15 @@ int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t
         // speculate that A has generic rank profile (keep a copy to fall back)
         const size_t mk = ws.mark();
         int32_t *backup = (int32_t *)ws.take((size_t)m * (size_t)n * 4);
+        const size_t nblk = (size_t)(((m < n ? m : n) + 63) / 64);
+        double *Li = (double *)ws.take(nblk * kBlk * sizeof(double));
+        double *Ui = (double *)ws.take(nblk * kBlk * sizeof(double));
         int *gflag = (int *)rank_dev + 4;
-        if (!backup) return FFP_E_WORKSPACE;
+        if (!backup || !Li || !Ui) return FFP_E_WORKSPACE;
         FFP_CHECK(copy2d(m, n, A, lda, backup, n, s));
         hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, gflag, 0);
         FFP_HIP_CHECK(hipGetLastError());
-        FFP_CHECK(lu_generic(c, m, n, A, lda, gflag));
+        FFP_CHECK(lu_generic(c, m, n, A, lda, gflag, Li, Ui));
         int64_t flag = 0;
         {
             std::lock_guard<std::mutex> g(g_pin_mu);
@@ -745,6 +780,11 @@ int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t
         }
         FFP_CHECK(copy2d(m, n, backup, n, A, lda, s));
         ws.release(mk);
+        if (flag != 1) {
+            // a leaf gave up waiting (see the generic leaf): report, A restored
+            FFP_HIP_CHECK(hipStreamSynchronize(s));
+            return FFP_E_INTERNAL;
+        }
     }
     return pluq_rec(c, m, n, A, lda, P, Q, r);
 }

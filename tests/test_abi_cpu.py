@@ -50,6 +50,8 @@ def test_scalar_helpers(lib):
     assert ffp.int8_limbs(2 * 127 * 257 + 1) == 2
     assert "ffpluq" in ffp.version()
     assert lib.ffp_error_string(-103) == b"workspace missing or too small"
+    for code in range(-101, -109, -1):  # every documented code has its own message
+        assert lib.ffp_error_string(code) not in (b"", b"unknown error")
 
 
 def test_argument_validation_before_device(lib):
