@@ -48,7 +48,7 @@ typedef void *ffp_stream_t; /* hipStream_t */
 #define FFP_E_RANGE (-105)       /* an input entry lies outside [0, p) (validating calls only) */
 #define FFP_E_UNSUPPORTED (-106) /* valid request this build does not implement */
 #define FFP_E_NODEVICE (-107)    /* no gfx950 device / kernels failed to load */
-#define FFP_E_INTERNAL (-108)    /* a device-side wait gave up (internal error); A is restored */
+#define FFP_E_INTERNAL (-108)    /* internal consistency check failed; A is restored */
 
 /* Largest p of each arithmetic path (see ffp_fgemm). */
 #define FFP_P_MAX_FP64 94906249u /* largest prime with (p-1)^2 + p < 2^53 */

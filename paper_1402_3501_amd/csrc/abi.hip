@@ -15,12 +15,15 @@ int resolve_path(int path, uint32_t p, int64_t m, int64_t n, int64_t k) {
     const int L = int8_limbs(p);
     if (L == 0) return FFP_PATH_FP64;
     // one limb: one INT8 product replaces one FP64 product at 64x the peak;
-    // three limbs: nine INT8 products, still ~7x the FP64 peak, once the
-    // product is large enough to amortise the limb split
-    // the limb split costs two extra launches and the INT8 tiles are 128 x 128:
-    // small products stay on the FP64 kernel
-    if (m * n < 256 * 256 || k < 128) return FFP_PATH_FP64;
-    return FFP_PATH_INT8;
+    // several limbs: L^2 INT8 products, still several times the FP64 peak,
+    // once the product amortises the limb split (one more launch) and fills
+    // the 128 x 128 INT8 tiles.  Measured on MI355X (p = 131071, whole-call
+    // time): FP64 wins every k <= 256 product below 2048 x 2048 outputs and
+    // INT8 every k >= 512 product from 512 x 512 up.
+    if (L == 1) return (k >= 128 && m * n >= 256 * 256) ? FFP_PATH_INT8 : FFP_PATH_FP64;
+    if (k >= 512 && m * n >= 512 * 512) return FFP_PATH_INT8;
+    if (k >= 256 && m * n >= 2048 * 2048) return FFP_PATH_INT8;
+    return FFP_PATH_FP64;
 }
 
 int fgemm_any(int path, const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
@@ -75,7 +78,7 @@ const char *ffp_error_string(int code) {
         case FFP_E_RANGE: return "input entry outside [0, p)";
         case FFP_E_UNSUPPORTED: return "unsupported request";
         case FFP_E_NODEVICE: return "no usable gfx950 device";
-        case FFP_E_INTERNAL: return "internal error: a device-side wait gave up";
+        case FFP_E_INTERNAL: return "internal consistency check failed";
         default: return code < 0 && code > -64 ? "invalid argument" : "unknown error";
     }
 }

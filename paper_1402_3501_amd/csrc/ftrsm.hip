@@ -168,6 +168,218 @@ __global__ __launch_bounds__(256) void k_trsm_apply(int db, int64_t nv, const do
             }
 }
 
+constexpr int kTBB = 256;  // fused base case: up to four 64-blocks
+
+// Fused base case for triangles of up to 256: one workgroup per 64 vectors
+// keeps its slab (d components x 64 vectors, centred int32) in LDS and runs
+// the block substitution
+//   X_t = W_t (B_t - sum_{s solved} M(t, s) X_s)
+// over the 64-blocks t in dependency order, every product on the FP64
+// matrix cores: 1 + 2 + .. + nb products of 64 x 64 x 64 in one launch
+// instead of nb applications and nb - 1 products in separate launches.  The
+// right-side solve is the same computation on the transposed slab (operands
+// transposed).  The next operand block is prefetched into registers while the
+// current product runs.
+//   M(t, s)[i][k] = direct ? T[64t + i][64s + k] : T[64s + k][64t + i]
+//   W_t = op(T)_tt^-1 (64 x 64 centred doubles), taken as is (left) or
+//   transposed (right).
+template <bool LEFT, bool RED>
+__global__ __launch_bounds__(256) void k_trsm_blk(int d, int64_t nv, const int32_t *__restrict__ T, int64_t ldt,
+                                                  int direct, int fwd, const double *__restrict__ W,
+                                                  int32_t *__restrict__ B, int64_t ldb, double p, double pinv,
+                                                  int32_t half, int ksteps) {
+    __shared__ int32_t S[kTBB][kTB + 1];  // [component][vector]
+    __shared__ double Ab[kTB][kTB + 2];   // current A operand
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
+    const int64_t v0 = (int64_t)blockIdx.x * kTB;
+    const int nb = (d + kTB - 1) / kTB;
+    const double hd = (double)half;
+    const int32_t ip = (int32_t)p;
+    // ---- slab in (clamped loads, zero outside)
+    {
+        constexpr int PER = kTBB * kTB / 256;
+        int32_t v[PER];
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * 256;
+            const int c = LEFT ? idx >> 6 : idx & 255, w = LEFT ? idx & 63 : idx >> 8;
+            const int cc = c < d ? c : d - 1;
+            const int64_t vv = v0 + w < nv ? v0 + w : nv - 1;
+            v[e] = LEFT ? B[(int64_t)cc * ldb + vv] : B[vv * ldb + cc];
+        }
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * 256;
+            const int c = LEFT ? idx >> 6 : idx & 255, w = LEFT ? idx & 63 : idx >> 8;
+            const int32_t x = (c < d && v0 + w < nv) ? v[e] : 0;
+            S[c][w] = x > half ? x - ip : x;
+        }
+    }
+    // items: for q = 0.., the sources r < q then the inverse of block q
+    const int nitems = nb * (nb + 1) / 2;
+    auto item = [&](int it, int &q, int &r) {
+        q = 0;
+        while ((q + 1) * (q + 2) / 2 <= it) ++q;
+        r = it - q * (q + 1) / 2;
+    };
+    auto blk = [&](int x) { return fwd ? x : nb - 1 - x; };
+    int32_t ri[16];
+    double rd[16];
+    auto prefetch = [&](int it) {
+        if (it >= nitems) return;
+        int q, r;
+        item(it, q, r);
+        const int t = blk(q);
+        if (r < q) {
+            const int sb = blk(r);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int idx = tid + e * 256, i = idx >> 6, k = idx & 63;
+                // direct: row 64t + i, column 64s + k; else row 64s + k, column 64t + i
+                // (clamped into the triangle; masked when staged)
+                const int a = direct ? 64 * t + i : 64 * sb + k, b = direct ? 64 * sb + k : 64 * t + i;
+                ri[e] = T[(int64_t)(a < d ? a : d - 1) * ldt + (b < d ? b : d - 1)];
+            }
+        } else {
+            const double *Wt = W + (int64_t)t * kTB * kTB;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) rd[e] = Wt[tid + e * 256];
+        }
+    };
+    v4d acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    // acc += Ab S[row0 .. row0 + 63][*]
+    auto product = [&](int row0, v4d (&ac)[2][2]) {
+        int steps = 0;
+#pragma unroll
+        for (int ks = 0; ks < kTB / 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            double a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = Ab[wm0 + i * 16 + (lane & 15)][kr];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) b[j] = (double)S[row0 + kr][wn0 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) ac[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], ac[i][j], 0, 0, 0);
+            if (RED && ++steps == ksteps) {
+                steps = 0;
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) ac[i][j][v] = mod_near(ac[i][j][v], p, pinv);
+            }
+        }
+        // keep partial sums bounded across several products
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) ac[i][j][v] = mod_near(ac[i][j][v], p, pinv);
+    };
+    prefetch(0);
+    __syncthreads();
+    for (int it = 0; it < nitems; ++it) {
+        int q, r;
+        item(it, q, r);
+        const int t = blk(q);
+        if (r == q && q > 0) {
+            // S_t <- S_t - (sum of the source products); lane l holds rows l/16 + 4v
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 64 * t + wm0 + i * 16 + (lane >> 4) + 4 * v, col = wn0 + j * 16 + (lane & 15);
+                        const double x = cmod((double)S[row][col] - acc[i][j][v], p, pinv, hd);
+                        S[row][col] = (int32_t)x;
+                        acc[i][j][v] = 0.0;
+                    }
+        }
+        // stage the operand block (M(t, s) masked to the triangle, or W_t)
+        if (r < q) {
+            const int sb = blk(r);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int idx = tid + e * 256, i = idx >> 6, k = idx & 63;
+                const bool in = 64 * t + i < d && 64 * sb + k < d;
+                const int32_t x = in ? ri[e] : 0;
+                Ab[i][k] = x > half ? (double)(x - ip) : (double)x;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int idx = tid + e * 256, i = idx >> 6, k = idx & 63;
+                if (LEFT) Ab[i][k] = rd[e];
+                else Ab[k][i] = rd[e];
+            }
+        }
+        __syncthreads();
+        prefetch(it + 1);
+        if (r < q) {
+            product(64 * blk(r), acc);
+        } else {
+            v4d x2[2][2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) x2[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+            product(64 * t, x2);
+            __syncthreads();  // every read of S_t is done
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 64 * t + wm0 + i * 16 + (lane >> 4) + 4 * v, col = wn0 + j * 16 + (lane & 15);
+                        S[row][col] = (int32_t)cmod(x2[i][j][v], p, pinv, hd);
+                    }
+        }
+        __syncthreads();
+    }
+    // ---- slab out
+    for (int idx = tid; idx < kTBB * kTB; idx += 256) {
+        const int c = LEFT ? idx >> 6 : idx & 255, w = LEFT ? idx & 63 : idx >> 8;
+        if (c < d && v0 + w < nv) {
+            const int32_t x = S[c][w];
+            const int32_t y = x < 0 ? x + ip : x;
+            if (LEFT) B[(int64_t)c * ldb + v0 + w] = y;
+            else B[(v0 + w) * ldb + c] = y;
+        }
+    }
+}
+
+static int trsm_blk(const Field &F, int side, int d, int64_t nv, const int32_t *T, int64_t ldt, bool direct,
+                    bool fwd, const double *W, int32_t *B, int64_t ldb, hipStream_t s) {
+    if (d <= 0 || nv <= 0) return FFP_OK;
+    const bool red = F.kexact < kTB;
+    const int ksteps = (int)(F.kexact / 4 < 1 ? 1 : (F.kexact / 4 > 16 ? 16 : F.kexact / 4));
+    dim3 grid((unsigned)((nv + kTB - 1) / kTB));
+#define FFP_TBK(L_, R_)                                                                                          \
+    hipLaunchKernelGGL((k_trsm_blk<L_, R_>), grid, dim3(256), 0, s, d, nv, T, ldt, (int)direct, (int)fwd, W, B, ldb, \
+                       F.pd, F.pinv, (int32_t)F.half, ksteps)
+    if (side == 0) {
+        if (red) FFP_TBK(true, true);
+        else FFP_TBK(true, false);
+    } else {
+        if (red) FFP_TBK(false, true);
+        else FFP_TBK(false, false);
+    }
+#undef FFP_TBK
+    FFP_HIP_CHECK(hipGetLastError());
+    return FFP_OK;
+}
+
 static int trsm_apply(const Field &F, int side, int db, int64_t nv, const double *W, int32_t *B, int64_t ldb,
                       hipStream_t s) {
     if (db <= 0 || nv <= 0) return FFP_OK;
@@ -191,15 +403,21 @@ static int trsm_apply(const Field &F, int side, int db, int64_t nv, const double
 }
 
 // op(T) = trans ? T^T : T.  eff_lower: op(T) is lower triangular.  Split
-// points are multiples of 64 from the origin of the top-level triangle, so
-// every base case is one of its diagonal blocks, whose inverse is W.
+// points are multiples of 256 from the origin of the top-level triangle, so
+// every base case is made of whole diagonal 64-blocks, whose inverses are W.
 static int trsm_rec(int path, const Field &F, int side, bool eff_lower, int trans, int64_t d, int64_t nv,
                     const int32_t *T, int64_t ldt, int32_t *B, int64_t ldb, const double *W, Arena &ws,
                     hipStream_t s) {
     if (d <= 0 || nv <= 0) return FFP_OK;
     const uint32_t minus1 = F.p - 1;
     if (d <= kTB) return trsm_apply(F, side, (int)d, nv, W, B, ldb, s);
-    const int64_t d1 = ((d / 2 + kTB - 1) / kTB) * kTB;  // < d for d > 64
+    if (d <= kTBB) {
+        const bool fwd = side == 0 ? eff_lower : !eff_lower;
+        const bool direct = (side == 0) == (trans == 0);
+        return trsm_blk(F, side, (int)d, nv, T, ldt, direct, fwd, W, B, ldb, s);
+    }
+    // split at a multiple of 256 (the fused base) below d
+    const int64_t d1 = ((d / 2 + kTBB - 1) / kTBB) * kTBB < d ? ((d / 2 + kTBB - 1) / kTBB) * kTBB : kTBB;
     const int64_t d2 = d - d1;
     const int32_t *T11 = T, *T22 = T + d1 * ldt + d1;
     const double *W1 = W, *W2 = W + (d1 / kTB) * kTB * kTB;

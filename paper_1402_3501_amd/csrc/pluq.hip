@@ -673,11 +673,11 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
 // multiple of 64,
 //   [A1 B1; C1 A4] = [L1 0; E L3] [U1 D; 0 U3],
 //   D = L1^-1 B1,  E = C1 U1^-1,  L3 U3 = A4 - E D,
-// so that every diagonal leaf is an aligned 64 x 64 block.  Each leaf stores
-// the inverses of its L and U blocks, which are exactly the base-case
-// inverses of the later solves with L1 and U1.  Leaves raise *gflag on the
-// first zero pivot (A is then not generic), and the caller restores A and
-// runs the general recursion.  The result, when the flag stays clear, is
+// so that every diagonal leaf is an aligned 64 x 64 block (the last one may
+// be smaller).  Each leaf stores the inverses of its L and U blocks, which
+// are exactly the base-case inverses of the later solves with L1 and U1.
+// Leaves raise *gflag on the first zero pivot (A is then not generic), and
+// the caller restores A and runs the general recursion.  The result, when the flag stays clear, is
 // bit-identical to the general one.
 namespace {
 constexpr int64_t kBlk = 64 * 64;  // doubles per stored block inverse
@@ -781,7 +781,7 @@ int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t
         FFP_CHECK(copy2d(m, n, backup, n, A, lda, s));
         ws.release(mk);
         if (flag != 1) {
-            // a leaf gave up waiting (see the generic leaf): report, A restored
+            // leaves only ever write 1: any other value is an internal error
             FFP_HIP_CHECK(hipStreamSynchronize(s));
             return FFP_E_INTERNAL;
         }
