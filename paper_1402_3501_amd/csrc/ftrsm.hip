@@ -170,40 +170,45 @@ __global__ __launch_bounds__(256) void k_trsm_apply(int db, int64_t nv, const do
 
 constexpr int kTBB = 256;  // fused base case: up to four 64-blocks
 
-// Fused base case for triangles of up to 256: one workgroup per 64 vectors
-// keeps its slab (d components x 64 vectors, centred int32) in LDS and runs
+// Fused base case for triangles of up to 256: one workgroup per 16 vectors
+// keeps its slab (d components x 16 vectors, centred int32) in LDS and runs
 // the block substitution
 //   X_t = W_t (B_t - sum_{s solved} M(t, s) X_s)
 // over the 64-blocks t in dependency order, every product on the FP64
-// matrix cores: 1 + 2 + .. + nb products of 64 x 64 x 64 in one launch
-// instead of nb applications and nb - 1 products in separate launches.  The
-// right-side solve is the same computation on the transposed slab (operands
-// transposed).  The next operand block is prefetched into registers while the
-// current product runs.
+// matrix cores: 1 + 2 + .. + nb products of 64 x 16 x 64 in one launch
+// instead of nb applications and nb - 1 products in separate launches.  A
+// product is one 16 x 16 output tile per wave (wave w: components
+// 16 w .. 16 w + 15 of the block); narrow slabs spread a solve over many
+// compute units, which is what bounds these small products.  The right-side
+// solve is the same computation on the transposed slab (operands
+// transposed).  Each wave reads its A-operand fragments straight from global
+// memory into registers, the next product's while the current one runs.
 //   M(t, s)[i][k] = direct ? T[64t + i][64s + k] : T[64s + k][64t + i]
 //   W_t = op(T)_tt^-1 (64 x 64 centred doubles), taken as is (left) or
 //   transposed (right).
+constexpr int kVB = 16;  // vectors per workgroup of the fused base case
+
 template <bool LEFT, bool RED>
 __global__ __launch_bounds__(256) void k_trsm_blk(int d, int64_t nv, const int32_t *__restrict__ T, int64_t ldt,
                                                   int direct, int fwd, const double *__restrict__ W,
                                                   int32_t *__restrict__ B, int64_t ldb, double p, double pinv,
                                                   int32_t half, int ksteps) {
-    __shared__ int32_t S[kTBB][kTB + 1];  // [component][vector]
-    __shared__ double Ab[kTB][kTB + 2];   // current A operand
+    constexpr int KS = kTB / 4;           // k-steps per 64 x 16 x 64 product
+    __shared__ int32_t S[kTBB][kVB + 1];  // [component][vector]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm0 = (wave >> 1) * 32, wn0 = (wave & 1) * 32;
-    const int64_t v0 = (int64_t)blockIdx.x * kTB;
+    const int r16 = lane & 15, k4 = lane >> 4;
+    const int64_t v0 = (int64_t)blockIdx.x * kVB;
     const int nb = (d + kTB - 1) / kTB;
     const double hd = (double)half;
     const int32_t ip = (int32_t)p;
     // ---- slab in (clamped loads, zero outside)
     {
-        constexpr int PER = kTBB * kTB / 256;
+        constexpr int PER = kTBB * kVB / 256;
         int32_t v[PER];
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * 256;
-            const int c = LEFT ? idx >> 6 : idx & 255, w = LEFT ? idx & 63 : idx >> 8;
+            const int c = LEFT ? idx >> 4 : idx & 255, w = LEFT ? idx & 15 : idx >> 8;
             const int cc = c < d ? c : d - 1;
             const int64_t vv = v0 + w < nv ? v0 + w : nv - 1;
             v[e] = LEFT ? B[(int64_t)cc * ldb + vv] : B[vv * ldb + cc];
@@ -211,7 +216,7 @@ __global__ __launch_bounds__(256) void k_trsm_blk(int d, int64_t nv, const int32
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * 256;
-            const int c = LEFT ? idx >> 6 : idx & 255, w = LEFT ? idx & 63 : idx >> 8;
+            const int c = LEFT ? idx >> 4 : idx & 255, w = LEFT ? idx & 15 : idx >> 8;
             const int32_t x = (c < d && v0 + w < nv) ? v[e] : 0;
             S[c][w] = x > half ? x - ip : x;
         }
@@ -224,8 +229,10 @@ __global__ __launch_bounds__(256) void k_trsm_blk(int d, int64_t nv, const int32
         r = it - q * (q + 1) / 2;
     };
     auto blk = [&](int x) { return fwd ? x : nb - 1 - x; };
-    int32_t ri[16];
-    double rd[16];
+    // A fragments of this lane: row 16 wave + r16 of the block, columns 4 ks + k4
+    const int arow = 16 * wave + r16;
+    int32_t ni[KS];
+    double nd[KS];
     auto prefetch = [&](int it) {
         if (it >= nitems) return;
         int q, r;
@@ -234,56 +241,39 @@ __global__ __launch_bounds__(256) void k_trsm_blk(int d, int64_t nv, const int32
         if (r < q) {
             const int sb = blk(r);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int idx = tid + e * 256, i = idx >> 6, k = idx & 63;
-                // direct: row 64t + i, column 64s + k; else row 64s + k, column 64t + i
-                // (clamped into the triangle; masked when staged)
-                const int a = direct ? 64 * t + i : 64 * sb + k, b = direct ? 64 * sb + k : 64 * t + i;
-                ri[e] = T[(int64_t)(a < d ? a : d - 1) * ldt + (b < d ? b : d - 1)];
+            for (int ks = 0; ks < KS; ++ks) {
+                const int k = 4 * ks + k4;
+                const int a = direct ? 64 * t + arow : 64 * sb + k, b = direct ? 64 * sb + k : 64 * t + arow;
+                ni[ks] = T[(int64_t)(a < d ? a : d - 1) * ldt + (b < d ? b : d - 1)];
             }
         } else {
             const double *Wt = W + (int64_t)t * kTB * kTB;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) rd[e] = Wt[tid + e * 256];
+            for (int ks = 0; ks < KS; ++ks) {
+                const int k = 4 * ks + k4;
+                nd[ks] = LEFT ? Wt[arow * kTB + k] : Wt[k * kTB + arow];
+            }
         }
     };
-    v4d acc[2][2];
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    // ac += A S[row0 .. row0 + 63][*], A in registers
+    auto product = [&](const double (&av)[KS], int row0, v4d &ac) {
+        int32_t bv[KS];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-    // acc += Ab S[row0 .. row0 + 63][*]
-    auto product = [&](int row0, v4d (&ac)[2][2]) {
+        for (int ks = 0; ks < KS; ++ks) bv[ks] = S[row0 + 4 * ks + k4][r16];
         int steps = 0;
 #pragma unroll
-        for (int ks = 0; ks < kTB / 4; ++ks) {
-            const int kr = ks * 4 + (lane >> 4);
-            double a[2], b[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = Ab[wm0 + i * 16 + (lane & 15)][kr];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) b[j] = (double)S[row0 + kr][wn0 + j * 16 + (lane & 15)];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) ac[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], ac[i][j], 0, 0, 0);
+        for (int ks = 0; ks < KS; ++ks) {
+            ac = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], (double)bv[ks], ac, 0, 0, 0);
             if (RED && ++steps == ksteps) {
                 steps = 0;
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) ac[i][j][v] = mod_near(ac[i][j][v], p, pinv);
+                for (int v = 0; v < 4; ++v) ac[v] = mod_near(ac[v], p, pinv);
             }
         }
         // keep partial sums bounded across several products
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) ac[i][j][v] = mod_near(ac[i][j][v], p, pinv);
+        for (int v = 0; v < 4; ++v) ac[v] = mod_near(ac[v], p, pinv);
     };
     prefetch(0);
     __syncthreads();
@@ -291,65 +281,46 @@ __global__ __launch_bounds__(256) void k_trsm_blk(int d, int64_t nv, const int32
         int q, r;
         item(it, q, r);
         const int t = blk(q);
-        if (r == q && q > 0) {
-            // S_t <- S_t - (sum of the source products); lane l holds rows l/16 + 4v
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int row = 64 * t + wm0 + i * 16 + (lane >> 4) + 4 * v, col = wn0 + j * 16 + (lane & 15);
-                        const double x = cmod((double)S[row][col] - acc[i][j][v], p, pinv, hd);
-                        S[row][col] = (int32_t)x;
-                        acc[i][j][v] = 0.0;
-                    }
-        }
-        // stage the operand block (M(t, s) masked to the triangle, or W_t)
+        // this item's operand (the prefetch registers are refilled below)
+        double av[KS];
         if (r < q) {
             const int sb = blk(r);
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int idx = tid + e * 256, i = idx >> 6, k = idx & 63;
-                const bool in = 64 * t + i < d && 64 * sb + k < d;
-                const int32_t x = in ? ri[e] : 0;
-                Ab[i][k] = x > half ? (double)(x - ip) : (double)x;
+            for (int ks = 0; ks < KS; ++ks) {
+                const bool in = 64 * t + arow < d && 64 * sb + 4 * ks + k4 < d;
+                const int32_t x = in ? ni[ks] : 0;
+                av[ks] = x > half ? (double)(x - ip) : (double)x;
             }
         } else {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int idx = tid + e * 256, i = idx >> 6, k = idx & 63;
-                if (LEFT) Ab[i][k] = rd[e];
-                else Ab[k][i] = rd[e];
-            }
+            for (int ks = 0; ks < KS; ++ks) av[ks] = nd[ks];
         }
-        __syncthreads();
         prefetch(it + 1);
         if (r < q) {
-            product(64 * blk(r), acc);
+            product(av, 64 * blk(r), acc);
         } else {
-            v4d x2[2][2];
+            // lane l holds rows l/16 + 4v of column l%16 of the wave's tile
+            if (q > 0) {
+                // S_t <- S_t - (sum of the source products)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) x2[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-            product(64 * t, x2);
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 64 * t + 16 * wave + k4 + 4 * v;
+                    S[row][r16] = (int32_t)cmod((double)S[row][r16] - acc[v], p, pinv, hd);
+                    acc[v] = 0.0;
+                }
+                __syncthreads();
+            }
+            v4d x2 = {0.0, 0.0, 0.0, 0.0};
+            product(av, 64 * t, x2);
             __syncthreads();  // every read of S_t is done
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int row = 64 * t + wm0 + i * 16 + (lane >> 4) + 4 * v, col = wn0 + j * 16 + (lane & 15);
-                        S[row][col] = (int32_t)cmod(x2[i][j][v], p, pinv, hd);
-                    }
+            for (int v = 0; v < 4; ++v) S[64 * t + 16 * wave + k4 + 4 * v][r16] = (int32_t)cmod(x2[v], p, pinv, hd);
+            __syncthreads();
         }
-        __syncthreads();
     }
     // ---- slab out
-    for (int idx = tid; idx < kTBB * kTB; idx += 256) {
-        const int c = LEFT ? idx >> 6 : idx & 255, w = LEFT ? idx & 63 : idx >> 8;
+    for (int idx = tid; idx < kTBB * kVB; idx += 256) {
+        const int c = LEFT ? idx >> 4 : idx & 255, w = LEFT ? idx & 15 : idx >> 8;
         if (c < d && v0 + w < nv) {
             const int32_t x = S[c][w];
             const int32_t y = x < 0 ? x + ip : x;
@@ -364,7 +335,7 @@ static int trsm_blk(const Field &F, int side, int d, int64_t nv, const int32_t *
     if (d <= 0 || nv <= 0) return FFP_OK;
     const bool red = F.kexact < kTB;
     const int ksteps = (int)(F.kexact / 4 < 1 ? 1 : (F.kexact / 4 > 16 ? 16 : F.kexact / 4));
-    dim3 grid((unsigned)((nv + kTB - 1) / kTB));
+    dim3 grid((unsigned)((nv + kVB - 1) / kVB));
 #define FFP_TBK(L_, R_)                                                                                          \
     hipLaunchKernelGGL((k_trsm_blk<L_, R_>), grid, dim3(256), 0, s, d, nv, T, ldt, (int)direct, (int)fwd, W, B, ldb, \
                        F.pd, F.pinv, (int32_t)F.half, ksteps)
