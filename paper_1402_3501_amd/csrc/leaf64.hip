@@ -41,6 +41,12 @@ __device__ __forceinline__ uint64_t first_k64(uint64_t x, int k) {
 
 enum { B_NONE = 0, B_ROW = 1, B_COL = 2 };
 
+// centred residue of an integer-valued double |x| < 2^53
+__device__ __forceinline__ double cen(double x, double p, double pinv, double hd) {
+    const double c = mod_canon(x, p, pinv);
+    return c > hd ? c - p : c;
+}
+
 template <bool RED, bool SMALLP>
 __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restrict__ A, int64_t lda,
                                               int32_t *__restrict__ P, int32_t *__restrict__ Q,
@@ -299,11 +305,10 @@ __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *_
                                                       double p, double pinv, int32_t half, int *__restrict__ gflag,
                                                       double *__restrict__ Linv, double *__restrict__ Uinv,
                                                       int inv_red, int kchunk) {
-    static_assert(NW == 8, "the inverse stage takes two groups of 256 threads");
+    static_assert(NW == 8, "four pivot rows per block share one row slot; two 256-thread inversion groups");
     constexpr int RPW = 64 / NW;  // rows per wave
+    constexpr int KB = 4;         // elimination steps per barrier
     if (__builtin_amdgcn_readfirstlane(*(volatile int *)gflag) != 0) return;
-    // the pivot-row slots are dead once the elimination is over and share
-    // their space with the buffers of the inverse stage
     // the pivot-row buffer is dead once the elimination is over and shares
     // its space with the buffers of the inverse stage
     struct InvBufs {
@@ -312,10 +317,10 @@ __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *_
         double Ts[2][kTri * kTri / 4];
     };
     __shared__ union {
-        double rowbuf[2][64];
+        double rowbuf[2][KB][64];
         InvBufs v;
     } sh;
-    __shared__ double qv[64], QI[64], SI[64], SQ[64];
+    __shared__ double qv[64], QI[64], SI[64];
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const double hd = (double)half;
     double R[RPW];
@@ -334,104 +339,118 @@ __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *_
         }
     }
     const int kd = mb < nb ? mb : nb;
+    // one fraction-free step on a row x held lane-wise: pivot row um (zero in
+    // columns <= k), pivot q, step k.  Columns <= k are multiplied by q
+    // instead of being left alone (no select); the final scaling divides the
+    // extra factors out again (see below).
+    auto step = [&](double x, double um, double q, int k) {
+        const double a = rld(x, k);
+        return mod_near(fma(-a, um, q * x), p, pinv);
+    };
+    // blocks of KB steps: rows kb .. kb + KB - 1 are rows e = kb / NW of waves
+    // kb % NW .. kb % NW + KB - 1 (KB divides NW)
 #pragma unroll
-    for (int kk = 0; kk < RPW; ++kk) {
-        // steps k = kk NW + w: row k is row kk of wave w
-        for (int w = 0; w < NW; ++w) {
-            const int k = kk * NW + w;
-            if (k >= kd) break;
-            if (wave == w) sh.rowbuf[k & 1][lane] = R[kk];
-            __syncthreads();
-            const double u = sh.rowbuf[k & 1][lane];
-            const double q = rld(u, k);
-            if (q == 0.0) {
-                // every wave sees the same pivot and leaves here
-                if (tid == 0) *gflag = 1;
-                return;
+    for (int kb = 0; kb < 64; kb += KB) {
+        if (kb < kd) {  // a guard, not a break: the loop must unroll (R[kb / NW])
+        const int nbk = kd - kb < KB ? kd - kb : KB;
+        const int eb = kb / NW, w0 = kb % NW;
+        const int buf = (kb / KB) & 1;
+        if (wave >= w0 && wave < w0 + nbk) sh.rowbuf[buf][wave - w0][lane] = R[eb];
+        __syncthreads();
+        // every wave eliminates the block's KB x 64 pivot rows among themselves
+        double u[KB], um[KB], q[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) u[j] = j < nbk ? sh.rowbuf[buf][j][lane] : 0.0;
+        bool zero = false;
+#pragma unroll
+        for (int j = 0; j < KB; ++j) {
+#pragma unroll
+            for (int jj = 0; jj < j; ++jj) u[j] = step(u[j], um[jj], q[jj], kb + jj);
+            q[j] = rld(u[j], kb + j);
+            um[j] = lane > kb + j ? u[j] : 0.0;
+            if (j < nbk && q[j] == 0.0) zero = true;
+        }
+        if (zero) {
+            // every wave sees the same pivots and leaves here
+            if (tid == 0) *gflag = 1;
+            return;
+        }
+        if (tid < nbk) qv[kb + tid] = tid == 0 ? q[0] : tid == 1 ? q[1] : tid == 2 ? q[2] : q[3];
+        // own rows: below the block, KB steps; in the block, the final pivot row
+#pragma unroll
+        for (int e = eb; e < RPW; ++e) {
+            const bool inblk = e == eb && wave >= w0 && wave < w0 + nbk;
+            const bool below = e > eb || wave >= w0 + nbk;  // rows after the block's pivots
+            if (inblk) {
+                const int j = wave - w0;
+                R[e] = j == 0 ? u[0] : j == 1 ? u[1] : j == 2 ? u[2] : u[3];
+            } else if (below) {
+                double x = R[e];
+#pragma unroll
+                for (int j = 0; j < KB; ++j)
+                    if (j < nbk) x = step(x, um[j], q[j], kb + j);
+                R[e] = x;
             }
-            if (tid == 0) qv[k] = q;
-            const bool cact = lane > k && lane < nb;
-            // rows below k: rows kk+1.. of each wave, row kk of the waves after w;
-            // all multipliers first, so that the row updates are independent
-            double a[RPW];
-#pragma unroll
-            for (int e = kk; e < RPW; ++e) a[e] = rld(R[e], k);
-#pragma unroll
-            for (int e = kk; e < RPW; ++e) {
-                const int i = wave + NW * e;
-                const bool below = e > kk || wave > w;  // uniform; computed either way
-                const double t = mod_near(fma(-a[e], u, q * R[e]), p, pinv);
-                R[e] = (below && i < mb && cact) ? t : R[e];
-            }
+        }
         }
     }
     __syncthreads();
     const bool want_inv = Linv != nullptr;
-    if (want_inv) {
-        for (int idx = tid; idx < kTri * (kTri + 1); idx += 64 * NW) {
-            (&sh.v.Ms[0][0][0])[idx] = 0;
-            (&sh.v.Ms[1][0][0])[idx] = 0;
-            (&sh.v.Ws[0][0][0])[idx] = 0.0;
-            (&sh.v.Ws[1][0][0])[idx] = 0.0;
-        }
-    }
     if (wave == 0) {
-        // q_t^-1 per lane, then exclusive prefix products s_t^-1 = q_0^-1 ... q_{t-1}^-1
-        double qi = 1.0;
+        // q_t^-1, s_t = q_0 .. q_{t-1} and s_t^-1 from one inverse (Montgomery):
+        // P_t = q_0 .. q_t, 1 / P_t = (1 / P_{k-1}) q_{t+1} .. q_{k-1}
+        double qc = 1.0;
         if (lane < kd) {
-            double qc = qv[lane];  // |qc| < p
-            if (qc < 0.0) qc += p;
-            qi = SMALLP ? (double)inv_mod_small((int32_t)qc, (int32_t)p) : (double)inv_mod((int32_t)qc, (int32_t)p);
-            if (qi > hd) qi -= p;
+            qc = qv[lane];  // |qc| < p
+            qc = cen(qc, p, pinv, hd);
         }
-        // inclusive scans of q^-1 and of q (the latter for U[t][t]^-1 = q_t^-1 s_t)
-        double sc = qi, sq = 1.0;
-        if (lane < kd) {
-            sq = qv[lane];
-            if (sq > hd) sq -= p;
-        }
+        double pre = qc, suf = qc;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            const double o = __shfl_up(sc, off), o2 = __shfl_up(sq, off);
-            if (lane >= off) {
-                const double c = mod_canon(sc * o, p, pinv), c2 = mod_canon(sq * o2, p, pinv);
-                sc = c > hd ? c - p : c;
-                sq = c2 > hd ? c2 - p : c2;
-            }
+            const double o = __shfl_up(pre, off), o2 = __shfl_down(suf, off);
+            if (lane >= off) pre = cen(pre * o, p, pinv, hd);
+            if (lane + off < 64) suf = cen(suf * o2, p, pinv, hd);
         }
-        double sx = __shfl_up(sc, 1), sqx = __shfl_up(sq, 1);
+        // pre = P_t (inclusive), suf = q_t .. q_63 (inclusive; q = 1 past k)
+        double total = rld(pre, 63);
+        if (total < 0.0) total += p;
+        double itot = SMALLP ? (double)inv_mod_uniform((int32_t)total, (int32_t)p)
+                             : (double)inv_mod((int32_t)total, (int32_t)p);
+        double sx = __shfl_down(suf, 1);   // q_{t+1} .. q_63
+        if (lane == 63) sx = 1.0;
+        const double invP = cen(itot * sx, p, pinv, hd);  // 1 / P_t
+        double pprev = __shfl_up(pre, 1), iprev = __shfl_up(invP, 1);
         if (lane == 0) {
-            sx = 1.0;
-            sqx = 1.0;
+            pprev = 1.0;
+            iprev = 1.0;
         }
-        QI[lane] = qi;
-        SI[lane] = sx;
-        SQ[lane] = sqx;
+        const double qi = cen(pprev * invP, p, pinv, hd);  // q_t^-1 = P_{t-1} / P_t
+        QI[lane] = cen(qi * pprev, p, pinv, hd);           // q_t^-1 s_t = U[t][t]^-1
+        SI[lane] = iprev;                                  // s_t^-1 = 1 / P_{t-1}
     }
     __syncthreads();
+    // Row i ends as s_i times its ordinary row in the columns c >= i (U part);
+    // its column c < min(i, k) holds the multiplier of step c times q_c ...
+    // q_{min(i,k)-1} (it was multiplied by every later pivot while i was below
+    // the pivot row), so L[i][c] = W[i][c] (q_c^-1 s_c) s_i^-1, with
+    // s_i = q_0 .. q_{min(i,k)-1}.
 #pragma unroll
     for (int e = 0; e < RPW; ++e) {
         const int i = wave + NW * e;
         const int lim = i < kd ? i : kd;
-        const double f = lane < lim ? QI[lane] : SI[i];
+        const double f = lane < lim ? cen(QI[lane] * SI[i], p, pinv, hd) : SI[i];
         const double v = mod_canon(R[e] * f, p, pinv);
         if (i < mb && lane < nb) A[(int64_t)i * lda + lane] = (int32_t)v;
         if (want_inv) {
-            // the k x k blocks: L strictly below the diagonal, U^T likewise
+            // the k x k blocks, written whole (no separate clearing): L strictly
+            // below the diagonal, U^T likewise; W holds the diagonal inverses
             const double cv = v > hd ? v - p : v;
-            if (i < kd && lane < kd) {
-                if (lane < i) sh.v.Ms[0][i][lane] = (int32_t)cv;
-                else if (lane > i) sh.v.Ms[1][lane][i] = (int32_t)cv;
-            }
-            if (lane == i) {
-                sh.v.Ws[0][i][i] = 1.0;
-                double ud = 1.0;  // U[i][i]^-1 = q_i^-1 s_i
-                if (i < kd) {
-                    const double c = mod_canon(QI[i] * SQ[i], p, pinv);
-                    ud = c > hd ? c - p : c;
-                }
-                sh.v.Ws[1][i][i] = ud;
-            }
+            const bool ink = i < kd && lane < kd;
+            sh.v.Ms[0][i][lane] = (ink && lane < i) ? (int32_t)cv : 0;
+            sh.v.Ms[1][lane][i] = (ink && lane > i) ? (int32_t)cv : 0;
+            const double ud = i < kd ? QI[i] : 1.0;  // U[i][i]^-1 = q_i^-1 s_i
+            sh.v.Ws[0][i][lane] = lane == i ? 1.0 : 0.0;
+            sh.v.Ws[1][i][lane] = lane == i ? ud : 0.0;
         }
     }
     if (!want_inv) return;
