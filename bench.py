@@ -181,6 +181,32 @@ def main():
             results[name] = Z
         if len(results) == 2:
             extra["fgemm_paths_bit_exact"] = bool(torch.equal(results["fp64"], results["int8"]))
+        del X, Y, results
+        # the batched persistent PLUQ on its own workload (4096 matrices,
+        # m, n uniform in [16, 512], ranks uniform in [1, min]); ranks checked
+        log("[bench] batched workload ...")
+        bs = wl.WORKLOADS["batch4096_p65521"]
+        ms_h, ns_h, rs_h, Ab_h, off_h = wl.make("batch4096_p65521")
+        ms_d = torch.from_numpy(ms_h).to(dev)
+        ns_d = torch.from_numpy(ns_h).to(dev)
+        off_d = torch.from_numpy(off_h).to(dev)
+        Ab0 = torch.from_numpy(Ab_h).to(dev)
+        Ab = Ab0.clone()
+        res = ffp.pluq_batched(ms_d, ns_d, Ab, off_d, bs["p"])
+        torch.cuda.synchronize()
+        Ab.copy_(Ab0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ffp.pluq_batched(ms_d, ns_d, Ab, off_d, bs["p"])
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        mm, nn, rr = (x.astype(np.float64) for x in (ms_h, ns_h, rs_h))
+        alg = float(np.sum(2 * mm * nn * rr - (mm + nn) * rr ** 2 + 2 * rr ** 3 / 3))
+        extra["batched_workload"] = "batch4096_p65521"
+        extra["batched_ms"] = round(tb * 1e3, 3)
+        extra["batched_matrices_per_s"] = round(len(ms_h) / tb, 1)
+        extra["batched_algorithmic_gops"] = round(alg / tb / 1e9, 3)
+        extra["batched_ranks_ok"] = bool(np.array_equal(res.rank.cpu().numpy()[:len(ms_h)], rs_h))
         out["extra"] = extra
 
     if not args.no_cpu:

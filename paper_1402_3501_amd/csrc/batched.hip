@@ -31,6 +31,7 @@ struct BFrame {
 
 struct BShared {
     uint32_t rowdone[kBW], coldone[kBW], mask[kBW];
+    uint32_t nz[kBW];  // row i has a nonzero in the active columns
     BFrame st[kBStack];
     int sp, type, bx, piv, r, job;
     int rord[kBMax], cord[kBMax];
@@ -65,13 +66,20 @@ __device__ static void bfirst_k(const uint32_t *m, int nw, int k, uint32_t *out)
     }
 }
 
-// one thread: walk to the next one-row / one-column region (or finish)
+// one thread: walk to the next one-row / one-column region (or finish).
+// Regions none of whose active rows has a nonzero in the active columns hold
+// no pivot and are skipped whole (S.nz); this only prunes the walk, the
+// regions that are visited and their order are those of the recursion.
 __device__ static void bwalk(BShared &S, int nwr, int nwc) {
     while (S.sp > 0) {
         BFrame &f = S.st[S.sp - 1];
         if (f.stage == 0) {
             const int nr = bpopc(f.rows, nwr), nc = bpopc(f.cols, nwc);
             if (nr == 0 || nc == 0) { S.sp--; continue; }
+            // no active row of the region has a nonzero left: no pivot in it
+            bool live = false;
+            for (int w = 0; w < nwr; ++w) live |= (f.rows[w] & ~S.rowdone[w] & S.nz[w]) != 0u;
+            if (!live) { S.sp--; continue; }
             if (nr == 1) {
                 S.type = BT_ROW;
                 S.bx = bfirst(f.rows, nwr);
@@ -144,8 +152,21 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
         const int m = m_arr[job], n = n_arr[job];
         int32_t *Aj = A + A_off[job];
         const int nwr = (m + 31) >> 5, nwc = (n + 31) >> 5;
-        // workspace copy (leading dimension n)
-        for (int64_t e = tid; e < (int64_t)m * n; e += kBT) W[e] = Aj[e];
+        // workspace copy (leading dimension n), and the nonzero-row mask
+        if (tid < kBW) S.nz[tid] = 0u;
+        __syncthreads();
+        {
+            const int wv = tid >> 6, ln = tid & 63;
+            for (int i = wv; i < m; i += kBT / 64) {
+                bool any = false;
+                for (int c = ln; c < n; c += 64) {
+                    const int32_t v = Aj[(int64_t)i * n + c];
+                    W[(int64_t)i * n + c] = v;
+                    any |= v != 0;
+                }
+                if (__ballot(any) != 0ull && ln == 0) atomicOr(&S.nz[i >> 5], 1u << (i & 31));
+            }
+        }
         if (tid == 0) {
             for (int w = 0; w < kBW; ++w) { S.rowdone[w] = 0; S.coldone[w] = 0; }
             BFrame &f = S.st[0];
@@ -172,11 +193,12 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
             if (type == BT_FIN) break;
             // search the region for its first nonzero (entries are canonical residues)
             if (type == BT_ROW) {
-                for (int c = tid; c < n; c += kBT)
-                    if (bbit(S.mask, c) && W[(int64_t)bx * n + c] != 0) { atomicMin(&S.piv, c); break; }
+                if (bbit(S.nz, bx))
+                    for (int c = tid; c < n; c += kBT)
+                        if (bbit(S.mask, c) && W[(int64_t)bx * n + c] != 0) { atomicMin(&S.piv, c); break; }
             } else {
                 for (int i = tid; i < m; i += kBT)
-                    if (bbit(S.mask, i) && W[(int64_t)i * n + bx] != 0) { atomicMin(&S.piv, i); break; }
+                    if (bbit(S.mask, i) && bbit(S.nz, i) && W[(int64_t)i * n + bx] != 0) { atomicMin(&S.piv, i); break; }
             }
             __syncthreads();
             const int pv = S.piv;
@@ -197,15 +219,62 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
                 W[(int64_t)i * n + y] = (int32_t)l;
             }
             __syncthreads();
-            // rank-one update of the active block
-            for (int i = 0; i < m; ++i) {
-                if (bbit(S.rowdone, i) || i == x) continue;  // uniform
-                const double l = S.vcol[i];
-                if (l == 0.0) continue;
-                int32_t *row = W + (int64_t)i * n;
-                for (int c = tid; c < n; c += kBT) {
-                    if (c == y || bbit(S.coldone, c)) continue;
-                    row[c] = (int32_t)mod_canon((double)row[c] - l * S.urow[c], p, pinv);
+            // rank-one update of the active block: wave w takes rows w*RU ..,
+            // RU rows at a time, lane c the columns c, c + 64, .., so that every
+            // lane has RU x CH independent loads in flight
+            {
+                constexpr int RU = 4, CH = 4;
+                const int wv = tid >> 6, ln = tid & 63, nch = (n + 63) >> 6;
+                for (int i0 = wv * RU; i0 < m; i0 += (kBT / 64) * RU) {
+                    double l[RU];
+                    bool nzr[RU];
+#pragma unroll
+                    for (int r = 0; r < RU; ++r) {
+                        const int i = i0 + r;
+                        const bool act = i < m && !bbit(S.rowdone, i) && i != x;
+                        l[r] = act ? S.vcol[i] : 0.0;
+                        nzr[r] = false;
+                    }
+                    for (int ch0 = 0; ch0 < nch; ch0 += CH) {
+                        int32_t v[RU][CH];
+                        double u[CH];
+                        bool ok[CH];
+#pragma unroll
+                        for (int cc = 0; cc < CH; ++cc) {
+                            const int c = ln + 64 * (ch0 + cc);
+                            ok[cc] = c < n && c != y && !bbit(S.coldone, c);
+                            u[cc] = ok[cc] ? S.urow[c] : 0.0;
+                        }
+#pragma unroll
+                        for (int r = 0; r < RU; ++r)
+#pragma unroll
+                            for (int cc = 0; cc < CH; ++cc) {
+                                const int c = ln + 64 * (ch0 + cc);
+                                v[r][cc] = (l[r] != 0.0 && ok[cc]) ? W[(int64_t)(i0 + r) * n + c] : 0;
+                            }
+#pragma unroll
+                        for (int r = 0; r < RU; ++r)
+#pragma unroll
+                            for (int cc = 0; cc < CH; ++cc) {
+                                const int c = ln + 64 * (ch0 + cc);
+                                if (l[r] != 0.0 && ok[cc]) {
+                                    const int32_t nv = (int32_t)mod_canon((double)v[r][cc] - l[r] * u[cc], p, pinv);
+                                    W[(int64_t)(i0 + r) * n + c] = nv;
+                                    nzr[r] |= nv != 0;
+                                }
+                            }
+                    }
+                    // rows with a nonzero multiplier changed: refresh their bit (a
+                    // row with a zero multiplier keeps its entries and its bit)
+#pragma unroll
+                    for (int r = 0; r < RU; ++r) {
+                        const bool any = __ballot(nzr[r]) != 0ull;
+                        const int i = i0 + r;
+                        if (ln == 0 && l[r] != 0.0) {
+                            if (any) atomicOr(&S.nz[i >> 5], 1u << (i & 31));
+                            else atomicAnd(&S.nz[i >> 5], ~(1u << (i & 31)));
+                        }
+                    }
                 }
             }
             if (tid == 0) {

@@ -115,7 +115,8 @@ def test_ftrsm_parity(lib, orc, p):
             for uplo in (0, 1):
                 for trans in (0, 1):
                     for diag in (0, 1):
-                        for (m, n) in [(5, 3), (70, 33), (200, 129)]:
+                        # d = 5 .. 600: the single-block, fused (<= 256) and recursive solves
+                        for (m, n) in [(5, 3), (70, 33), (200, 129), (257, 40), (40, 600)]:
                             d = m if side == 0 else n
                             T = rng.integers(0, p, (d, d)).astype(np.int32)
                             T[np.arange(d), np.arange(d)] = rng.integers(1, p, d)
