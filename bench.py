@@ -11,9 +11,12 @@ effective rate.
 Also printed (outside the timed steps): the same PLUQ on the other path,
 the 8192^3 fgemm on both paths, and bit-exact agreement between paths.
 
-The roofline object is for the dominant kernel (the modular matrix product),
-from HIP events that the library records around each of its launches on the
-launching stream during the timed steps.  The CPU baseline is the plain
+The roofline object is for the dominant contraction kernel (the modular
+matrix product family with the most time in the step), from HIP events that
+the library records around each of its launches on the launching stream
+during the timed steps; share_of_step says how much of the step it covers
+(the single-workgroup leaf and the triangular solves are latency-bound and
+take the rest).  The CPU baseline is the plain
 oracle on a bounded sample (the leading 4096 x 4096 block of the same matrix).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--path auto|fp64|int8]
@@ -36,6 +39,26 @@ PEAK_INT8 = 5.0e15       # dense INT8 matrix peak, MI355X
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def measured_traffic(family: str):
+    """HBM bytes per launch of a product kernel family, from the committed
+    rocprofv3 counter summary, or None when that summary is missing or was
+    taken on a different source of the kernel."""
+    import hashlib
+    import re
+    src = {"k_fgemm_f64": "fgemm_f64.hip", "k_fgemm_i8": "fgemm_i8.hip"}[family]
+    prof = os.path.join(ROOT, "profiles", family.replace("k_", "") + "_pluq8192_p131071_traffic.md")
+    try:
+        text = open(prof).read()
+        sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1402_3501_amd", "csrc", src), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m1 = re.search(r"source_sha256: ([0-9a-f]{64})", text)
+    m2 = re.search(r"traffic_bytes_per_launch: ([0-9.]+)", text)
+    if not m1 or not m2 or m1.group(1) != sha:
+        return None
+    return float(m2.group(1))
 
 
 def main():
@@ -118,12 +141,15 @@ def main():
             roof = {"bound": "mfma", "achieved": kops / (kms * 1e-3) / 1e12, "peak": PEAK_FP64 / 1e12,
                     "unit": "TFLOP/s"}
         roof["frac"] = roof["achieved"] / roof["peak"]
-        roof["traffic"] = None
-        roof["kernel"] = "k_fgemm_i8" if dom == ffp.PATH_INT8 else "k_fgemm_f64"
+        family = "k_fgemm_i8" if dom == ffp.PATH_INT8 else "k_fgemm_f64"
+        roof["traffic"] = measured_traffic(family)
+        roof["kernel"] = family
+        roof["algorithmic_bytes_per_launch"] = ffp.profile_read_bytes(dom) / launches
         roof["launches_per_step"] = launches / max(args.steps, 1)
         roof["avg_launch_us"] = kms * 1e3 / launches
         roof["field_ops_per_launch"] = kops / launches
         roof["kernel_ms_per_step"] = kms / max(args.steps, 1)
+        roof["share_of_step"] = roof["kernel_ms_per_step"] / ms
         other = ffp.PATH_FP64 if dom == ffp.PATH_INT8 else ffp.PATH_INT8
         roof["other_path_kernel_ms_per_step"] = prof[other][1] / max(args.steps, 1)
 

@@ -193,6 +193,10 @@ int ffp_swaps_to_perm(int64_t len, const int32_t *ipiv, int32_t *perm);
 int ffp_profile_enable(int on);
 int ffp_profile_reset(void);
 int ffp_profile_read(int path, int64_t *launches, double *milliseconds, double *field_ops);
+/* the summed algorithmic memory traffic of the same launches: operands read
+ * once and the result written once, (m k + k n + m n [+ m n if beta != 0]) * 4
+ * bytes per product (the INT8 path counts its int32 operands, not the limbs) */
+int ffp_profile_read_bytes(int path, double *bytes);
 
 #ifdef __cplusplus
 }

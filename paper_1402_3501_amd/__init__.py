@@ -65,6 +65,7 @@ def load():
         "ffp_profile_reset": ([], i32),
         "ffp_profile_read": ([i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double)], i32),
+        "ffp_profile_read_bytes": ([i32, ctypes.POINTER(ctypes.c_double)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -308,3 +309,10 @@ def profile_read(path: int):
     _check(load().ffp_profile_read(path, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(ops)),
            "ffp_profile_read")
     return int(n.value), float(ms.value), float(ops.value)
+
+
+def profile_read_bytes(path: int) -> float:
+    """Algorithmic bytes (operands read once, result written once) of the same launches."""
+    b = ctypes.c_double(0)
+    _check(load().ffp_profile_read_bytes(path, ctypes.byref(b)), "ffp_profile_read_bytes")
+    return float(b.value)

@@ -9,6 +9,7 @@ namespace ffp {
 int profile_enable(int on);
 int profile_reset();
 int profile_read(int path, int64_t *launches, double *ms, double *ops);
+int profile_read_bytes(int path, double *bytes);
 
 int resolve_path(int path, uint32_t p, int64_t m, int64_t n, int64_t k) {
     if (path != FFP_PATH_AUTO) return path;
@@ -335,5 +336,6 @@ int ffp_profile_reset(void) { return profile_reset(); }
 int ffp_profile_read(int path, int64_t *launches, double *milliseconds, double *field_ops) {
     return profile_read(path, launches, milliseconds, field_ops);
 }
+int ffp_profile_read_bytes(int path, double *bytes) { return profile_read_bytes(path, bytes); }
 
 }  // extern "C"

@@ -90,7 +90,7 @@ void *Arena::take(size_t bytes) {
 namespace {
 struct ProfRec {
     int path;
-    double ops;
+    double ops, bytes;
     hipEvent_t e0, e1;
 };
 std::mutex g_prof_mu;
@@ -99,7 +99,7 @@ std::vector<ProfRec> g_prof;
 std::vector<hipEvent_t> g_pool;  // recycled events (creation is the costly part)
 struct ProfTotals {
     int64_t launches = 0;
-    double ms = 0.0, ops = 0.0;
+    double ms = 0.0, ops = 0.0, bytes = 0.0;
 } g_tot[3];
 
 hipEvent_t pool_get() {
@@ -122,6 +122,7 @@ void drain_locked() {
             g_tot[r.path].launches += 1;
             g_tot[r.path].ms += ms;
             g_tot[r.path].ops += r.ops;
+            g_tot[r.path].bytes += r.bytes;
         }
         g_pool.push_back(r.e0);
         g_pool.push_back(r.e1);
@@ -130,7 +131,8 @@ void drain_locked() {
 }
 }  // namespace
 
-ProfScope::ProfScope(int path_, double ops_, hipStream_t s_) : path(path_), ops(ops_), s(s_) {
+ProfScope::ProfScope(int path_, double ops_, hipStream_t s_, double bytes_)
+    : path(path_), ops(ops_), bytes(bytes_), s(s_) {
     if (!g_prof_on) return;
     std::lock_guard<std::mutex> g(g_prof_mu);
     hipEvent_t a = pool_get(), b = pool_get();
@@ -148,7 +150,7 @@ ProfScope::~ProfScope() {
     if (!ev0) return;
     (void)hipEventRecord((hipEvent_t)ev1, s);
     std::lock_guard<std::mutex> g(g_prof_mu);
-    g_prof.push_back({path, ops, (hipEvent_t)ev0, (hipEvent_t)ev1});
+    g_prof.push_back({path, ops, bytes, (hipEvent_t)ev0, (hipEvent_t)ev1});
 }
 
 int profile_enable(int on) {
@@ -169,6 +171,13 @@ int profile_read(int path, int64_t *launches, double *ms, double *ops) {
     if (launches) *launches = g_tot[path].launches;
     if (ms) *ms = g_tot[path].ms;
     if (ops) *ops = g_tot[path].ops;
+    return FFP_OK;
+}
+int profile_read_bytes(int path, double *bytes) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    drain_locked();
+    if (path < 0 || path > 2) return -1;
+    if (bytes) *bytes = g_tot[path].bytes;
     return FFP_OK;
 }
 

@@ -57,10 +57,10 @@ struct Arena {
 // ------------------------------------------------------------------ profiling
 struct ProfScope {
     int path;
-    double ops;
+    double ops, bytes;
     hipStream_t s;
     void *ev0 = nullptr, *ev1 = nullptr;
-    ProfScope(int path_, double ops_, hipStream_t s_);
+    ProfScope(int path_, double ops_, hipStream_t s_, double bytes_ = 0.0);
     ~ProfScope();
 };
 

@@ -453,7 +453,8 @@ int fgemm_f64(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, u
     const double p = F.pd, pinv = F.pinv, a = (double)alpha, b = (double)beta;
     const int32_t half = (int32_t)F.half;
     const int64_t big_tiles = ((m + 127) / 128) * ((n + 127) / 128);
-    ProfScope prof(FFP_PATH_FP64, 2.0 * (double)m * (double)n * (double)k, s);
+    ProfScope prof(FFP_PATH_FP64, 2.0 * (double)m * (double)n * (double)k, s,
+                   4.0 * ((double)m * (double)k + (double)k * (double)n + (beta != 0 ? 2.0 : 1.0) * (double)m * (double)n));
     if (big_tiles >= 192) {
         dim3 grid((unsigned)((n + 127) / 128), (unsigned)((m + 127) / 128));
         if (red) launch_tiles<128, 128, true>(ta, tb, grid, s, m, n, k, A, lda, B, ldb, C, ldc, p, pinv, half, a, b, ksteps);

@@ -264,7 +264,9 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
                            sb, Mp / 64, kc, Kp, (int32_t)F.half, (int32_t)F.p);
         const double be = kc0 == 0 ? (double)beta : 1.0;
         {
-            ProfScope prof(FFP_PATH_INT8, 2.0 * (double)m * (double)n * (double)kc, s);
+            ProfScope prof(FFP_PATH_INT8, 2.0 * (double)m * (double)n * (double)kc, s,
+                           4.0 * ((double)m * (double)kc + (double)kc * (double)n +
+                                  (be != 0.0 ? 2.0 : 1.0) * (double)m * (double)n));
             hipLaunchKernelGGL((k_fgemm_i8<L>), dim3((unsigned)(Np / kI8BN), (unsigned)(Mp / kI8BM)), dim3(kI8Threads),
                                0, s, Ad, Bd, Kp, planeA, planeB, m, n, C, ldc, F.pd, F.pinv, (double)alpha, be,
                                wts[0], wts[1], wts[2], wts[3]);
