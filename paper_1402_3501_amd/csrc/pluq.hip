@@ -695,6 +695,15 @@ int node_updates_gen(Ctx &c, int64_t m, int64_t n, int64_t h, int32_t *A, int64_
     a2.base = (char *)ws.take(need);
     a2.cap = need;
     if (!a2.base) return FFP_E_WORKSPACE;
+    // below 256 the two solves are a few microseconds each, less than the
+    // cross-stream fork and join cost (measured on MI355X): one stream
+    if (h < 256) {
+        FFP_CHECK(ftrsm_with_inverses(c.path, F, 1, false, m - h, h, A, lda, A + h * lda, lda, Ui, a2, c.s));
+        FFP_CHECK(ftrsm_with_inverses(c.path, F, 0, true, h, n - h, A, lda, A + h, lda, Li, ws, c.s));
+        FFP_CHECK(fgemm_sub(c, m - h, n - h, h, A + h * lda, lda, A + h, lda, A + h * lda + h, lda));
+        ws.release(mk);
+        return FFP_OK;
+    }
     hipEvent_t fork, join;
     FFP_CHECK(ev_get(&fork));
     FFP_CHECK(ev_get(&join));
