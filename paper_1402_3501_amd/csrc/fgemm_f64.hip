@@ -298,92 +298,84 @@ __global__ __launch_bounds__(256) void k_fgemm_f64_k64(int64_t m, int64_t n, int
             }
 }
 
-// Small products: one wave per 32 x 32 output tile, so that a product of a
-// few 64 x 64 blocks is spread over many compute units instead of running
-// as one long workgroup.  K is staged 32 at a time (the next slice is loaded
-// while the current one is multiplied); loads are unconditional with
-// clamped 32-bit indices; for the common alpha = +-1, beta in {0, 1} the
-// epilogue is a single reduction of +-acc + C.
+// Small products: one 32 x 32 output tile per workgroup of four waves that
+// split K (wave w takes the 32-deep K stages w, w + 4, ...), so a product of
+// a few 64 x 64 blocks keeps the matrix cores of four SIMDs busy on each of
+// many compute units instead of one long wave.  Operands go straight from
+// global memory to registers, one stage ahead: at k-step s of a stage, lane
+// l supplies row l % 16 and the reduction index 8 (l / 16) + s (the order of
+// the sum is free), so each lane reads 8 consecutive entries of a row-major
+// operand (two 16-byte loads when aligned) and the other operand is read
+// with 16 lanes along its contiguous dimension.  Loads are unconditional
+// with clamped 32-bit indices and masked after arrival.  The four partial
+// tiles, each reduced to |x| <= p/2, are summed through LDS; for alpha = +-1
+// and beta in {0, 1} the epilogue is one reduction of +-acc + C.
 template <bool TA, bool TB, bool RED>
-__global__ __launch_bounds__(64) void k_fgemm_f64_t32(int m, int n, int k, const int32_t *__restrict__ A,
+__global__ __launch_bounds__(256) void k_fgemm_f64_sk(int m, int n, int k, const int32_t *__restrict__ A,
                                                       uint32_t lda, const int32_t *__restrict__ B, uint32_t ldb,
                                                       int32_t *__restrict__ C, uint32_t ldc, double p, double pinv,
-                                                      int32_t half, double alpha, double beta, int kchunk_steps) {
-    constexpr int T = 32;
-    __shared__ int32_t As[2][T][T + 1];  // [kk][i]
-    __shared__ int32_t Bs[2][T][T + 1];  // [kk][j]
-    const int lane = threadIdx.x;
+                                                      int32_t half, double alpha, double beta, int kchunk_steps,
+                                                      int vecA, int vecB) {
+    constexpr int T = 32, KD = 32, NWV = 4;
+    __shared__ double part[NWV][T][T + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, kq = lane >> 4;
     const int m0 = blockIdx.y * T, n0 = blockIdx.x * T;
     const int32_t ip = (int32_t)p;
-    const int x = lane & 31, y0 = lane >> 5;  // element (x along the contiguous dimension, y0 + 2e)
-    int32_t ra[16], rb[16];
-    auto load = [&](int k0) {
+    const int nst = (k + KD - 1) / KD;
+    // one operand's 2 x 8 entries of a stage: rows (or columns) 16 u + r16
+    // of the tile, reduction indices k0 + 8 kq + s
+    auto load_op = [&](const int32_t *__restrict__ X, uint32_t ldx, bool kcontig, int vec, int base, int lim, int k0,
+                       int32_t (&r)[2][8]) {
+        const int kb = k0 + 8 * kq;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int y = y0 + 2 * e;
-            {
-                const int i = TA ? x : y, kk = TA ? y : x;
-                const int ci = min(m0 + i, m - 1), ck = min(k0 + kk, k - 1);
-                ra[e] = TA ? A[(uint64_t)ck * lda + ci] : A[(uint64_t)ci * lda + ck];
-            }
-            {
-                const int j = TB ? y : x, kk = TB ? x : y;
-                const int cj = min(n0 + j, n - 1), ck = min(k0 + kk, k - 1);
-                rb[e] = TB ? B[(uint64_t)cj * ldb + ck] : B[(uint64_t)ck * ldb + cj];
-            }
-        }
-    };
-    auto store = [&](int buf, int k0) {
+        for (int u = 0; u < 2; ++u) {
+            const int g = min(base + 16 * u + r16, lim - 1);
+            if (kcontig) {
+                const int32_t *row = X + (uint64_t)g * ldx;
+                if (vec && kb + 8 <= k) {
+                    const int4 x = *(const int4 *)(row + kb), y = *(const int4 *)(row + kb + 4);
+                    r[u][0] = x.x; r[u][1] = x.y; r[u][2] = x.z; r[u][3] = x.w;
+                    r[u][4] = y.x; r[u][5] = y.y; r[u][6] = y.z; r[u][7] = y.w;
+                } else {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int y = y0 + 2 * e;
-            {
-                const int i = TA ? x : y, kk = TA ? y : x;
-                const int32_t v = (m0 + i < m && k0 + kk < k) ? ra[e] : 0;
-                As[buf][kk][i] = v > half ? v - ip : v;
-            }
-            {
-                const int j = TB ? y : x, kk = TB ? x : y;
-                const int32_t v = (n0 + j < n && k0 + kk < k) ? rb[e] : 0;
-                Bs[buf][kk][j] = v > half ? v - ip : v;
-            }
-        }
-    };
-    int32_t cpre[2][2][4];
-    if (beta != 0.0) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int gi = min(m0 + i * 16 + (lane >> 4) + 4 * v, m - 1), gj = min(n0 + j * 16 + (lane & 15), n - 1);
-                    cpre[i][j][v] = C[(uint64_t)gi * ldc + gj];
+                    for (int t = 0; t < 8; ++t) r[u][t] = row[min(kb + t, k - 1)];
                 }
+            } else {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) r[u][t] = X[(uint64_t)min(kb + t, k - 1) * ldx + g];
+            }
+        }
+    };
+    auto load = [&](int k0, int32_t (&ra)[2][8], int32_t (&rb)[2][8]) {
+        load_op(A, lda, !TA, vecA, m0, m, k0, ra);
+        load_op(B, ldb, TB, vecB, n0, n, k0, rb);
+    };
+    // this thread's four entries of C for the epilogue, read up front
+    int32_t cv[T * T / 256];
+#pragma unroll
+    for (int e = 0; e < T * T / 256; ++e) {
+        const int idx = tid + 256 * e;
+        cv[e] = beta != 0.0 ? C[(uint64_t)min(m0 + (idx >> 5), m - 1) * ldc + min(n0 + (idx & 31), n - 1)] : 0;
     }
     v4d acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
-    const int nt = (k + T - 1) / T;
     int steps = 0;
-    if (nt > 0) {
-        load(0);
-        store(0, 0);
-    }
-    __syncthreads();
-    for (int t = 0; t < nt; ++t) {
-        const int buf = t & 1;
-        if (t + 1 < nt) load((t + 1) * T);
+    auto compute = [&](int k0, const int32_t (&ra)[2][8], const int32_t (&rb)[2][8]) {
 #pragma unroll
-        for (int ks = 0; ks < T / 4; ++ks) {
-            const int kr = ks * 4 + (lane >> 4);
+        for (int t = 0; t < 8; ++t) {
+            const bool kin = k0 + 8 * kq + t < k;
             double a[2], b[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = (double)As[buf][kr][i * 16 + (lane & 15)];
-#pragma unroll
-            for (int j = 0; j < 2; ++j) b[j] = (double)Bs[buf][kr][j * 16 + (lane & 15)];
+            for (int u = 0; u < 2; ++u) {
+                const int32_t va = (kin && m0 + 16 * u + r16 < m) ? ra[u][t] : 0;
+                const int32_t vb = (kin && n0 + 16 * u + r16 < n) ? rb[u][t] : 0;
+                a[u] = (double)(va > half ? va - ip : va);
+                b[u] = (double)(vb > half ? vb - ip : vb);
+            }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -399,34 +391,52 @@ __global__ __launch_bounds__(64) void k_fgemm_f64_t32(int m, int n, int k, const
                         for (int v = 0; v < 4; ++v) acc[i][j][v] = mod_near(acc[i][j][v], p, pinv);
             }
         }
-        if (t + 1 < nt) store(buf ^ 1, (t + 1) * T);
-        __syncthreads();
+    };
+    {
+        int32_t a0[2][8], b0[2][8], a1[2][8], b1[2][8];
+        int st = wave;
+        if (st < nst) load(st * KD, a0, b0);
+        while (st < nst) {
+            if (st + NWV < nst) load((st + NWV) * KD, a1, b1);
+            compute(st * KD, a0, b0);
+            st += NWV;
+            if (st >= nst) break;
+            if (st + NWV < nst) load((st + NWV) * KD, a0, b0);
+            compute(st * KD, a1, b1);
+            st += NWV;
+        }
     }
-    // +-1 and beta in {0, 1}: one reduction of sign * acc + C (exact: |acc| < 2^53 - p)
-    const double sgn = alpha == 1.0 ? 1.0 : (alpha == p - 1.0 ? -1.0 : 0.0);
-    const bool fast = sgn != 0.0 && (beta == 0.0 || beta == 1.0);
+    // lane l holds rows l/16 + 4v of column l%16 of each 16 x 16 block
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int gi = m0 + i * 16 + (lane >> 4) + 4 * v, gj = n0 + j * 16 + (lane & 15);
-                double r;
-                if (fast) {
-                    r = mod_canon(fma(sgn, acc[i][j][v], beta != 0.0 ? (double)cpre[i][j][v] : 0.0), p, pinv);
-                } else {
-                    r = mod_canon(acc[i][j][v], p, pinv);
-                    if (alpha != 1.0) r = mod_canon(alpha * r, p, pinv);
-                    if (beta != 0.0) {
-                        double c = (double)cpre[i][j][v];
-                        if (beta != 1.0) c = mod_canon(beta * c, p, pinv);
-                        r += c;
-                        if (r >= p) r -= p;
-                    }
-                }
-                if (gi < m && gj < n) C[(uint64_t)gi * ldc + gj] = (int32_t)r;
+            for (int v = 0; v < 4; ++v)
+                part[wave][i * 16 + kq + 4 * v][j * 16 + r16] = mod_near(acc[i][j][v], p, pinv);
+    __syncthreads();
+    const double sgn = alpha == 1.0 ? 1.0 : (alpha == p - 1.0 ? -1.0 : 0.0);
+    const bool fast = sgn != 0.0 && (beta == 0.0 || beta == 1.0);
+#pragma unroll
+    for (int e = 0; e < T * T / 256; ++e) {
+        const int idx = tid + 256 * e, li = idx >> 5, lj = idx & 31;
+        const int gi = m0 + li, gj = n0 + lj;
+        const double x = part[0][li][lj] + part[1][li][lj] + part[2][li][lj] + part[3][li][lj];
+        double r;
+        if (fast) {
+            r = mod_canon(fma(sgn, x, (double)cv[e]), p, pinv);
+        } else {
+            r = mod_canon(x, p, pinv);
+            if (alpha != 1.0) r = mod_canon(alpha * r, p, pinv);
+            if (beta != 0.0) {
+                double c = (double)cv[e];
+                if (beta != 1.0) c = mod_canon(beta * c, p, pinv);
+                r += c;
+                if (r >= p) r -= p;
             }
+        }
+        if (gi < m && gj < n) C[(uint64_t)gi * ldc + gj] = (int32_t)r;
+    }
 }
 
 template <int BM, int BN, bool RED>
@@ -459,12 +469,15 @@ int fgemm_f64(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, u
         dim3 grid((unsigned)((n + 127) / 128), (unsigned)((m + 127) / 128));
         if (red) launch_tiles<128, 128, true>(ta, tb, grid, s, m, n, k, A, lda, B, ldb, C, ldc, p, pinv, half, a, b, ksteps);
         else launch_tiles<128, 128, false>(ta, tb, grid, s, m, n, k, A, lda, B, ldb, C, ldc, p, pinv, half, a, b, ksteps);
-    } else if (((m + 63) / 64) * ((n + 63) / 64) < 256 && m < (1ll << 30) && n < (1ll << 30) && k < (1ll << 30) &&
+    } else if ((((m + 63) / 64) * ((n + 63) / 64) < 256 || k <= 256) && m < (1ll << 30) && n < (1ll << 30) && k < (1ll << 30) &&
                lda < (1ll << 31) && ldb < (1ll << 31) && ldc < (1ll << 31)) {
         dim3 grid((unsigned)((n + 31) / 32), (unsigned)((m + 31) / 32));
+        // 16-byte loads along K need 16-byte aligned rows
+        const int vA = ((((uintptr_t)A) | (uintptr_t)(lda * 4)) & 15) == 0;
+        const int vB = ((((uintptr_t)B) | (uintptr_t)(ldb * 4)) & 15) == 0;
 #define FFP_T32(TA_, TB_, R_)                                                                               \
-    hipLaunchKernelGGL((k_fgemm_f64_t32<TA_, TB_, R_>), grid, dim3(64), 0, s, (int)m, (int)n, (int)k, A,    \
-                       (uint32_t)lda, B, (uint32_t)ldb, C, (uint32_t)ldc, p, pinv, half, a, b, ksteps)
+    hipLaunchKernelGGL((k_fgemm_f64_sk<TA_, TB_, R_>), grid, dim3(256), 0, s, (int)m, (int)n, (int)k, A,    \
+                       (uint32_t)lda, B, (uint32_t)ldb, C, (uint32_t)ldc, p, pinv, half, a, b, ksteps, vA, vB)
 #define FFP_T32R(R_)                                          \
     if (!ta && !tb) FFP_T32(false, false, R_);                 \
     else if (ta && !tb) FFP_T32(true, false, R_);              \

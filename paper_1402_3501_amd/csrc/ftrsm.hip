@@ -182,7 +182,7 @@ constexpr int kTBB = 256;  // fused base case: up to four 64-blocks
 // compute units, which is what bounds these small products.  The right-side
 // solve is the same computation on the transposed slab (operands
 // transposed).  Each wave reads its A-operand fragments straight from global
-// memory into registers, the next product's while the current one runs.
+// memory into registers, three products ahead of the one that runs.
 //   M(t, s)[i][k] = direct ? T[64t + i][64s + k] : T[64s + k][64t + i]
 //   W_t = op(T)_tt^-1 (64 x 64 centred doubles), taken as is (left) or
 //   transposed (right).
@@ -229,29 +229,71 @@ __global__ __launch_bounds__(256) void k_trsm_blk(int d, int64_t nv, const int32
         r = it - q * (q + 1) / 2;
     };
     auto blk = [&](int x) { return fwd ? x : nb - 1 - x; };
-    // A fragments of this lane: row 16 wave + r16 of the block, columns 4 ks + k4
+    // A fragments of this lane: row 16 wave + r16 of the block, and the
+    // reduction index k = 16 k4 + ks at k-step ks (the sum over k may run in
+    // any order as long as the S operand uses the same one), so that each
+    // lane reads 16 consecutive entries of a row of T or W
     const int arow = 16 * wave + r16;
-    int32_t ni[KS];
-    double nd[KS];
-    auto prefetch = [&](int it) {
-        if (it >= nitems) return;
+    const bool vec = (((uintptr_t)T | (uintptr_t)(ldt * 4)) & 15) == 0;
+    // operand fragments in flight: a ring of PD raw slots (16 int32 entries
+    // of T, or 16 doubles of W as 32 words), filled PD items ahead so that
+    // several global reads overlap the products
+    constexpr int PD = RED ? 1 : 3;  // the reducing variant has no registers to spare
+    constexpr int MAXIT = (kTBB / kTB) * (kTBB / kTB + 1) / 2;
+    uint32_t ring[PD][2 * KS];
+    auto prefetch = [&](int it, uint32_t(&sl)[2 * KS]) {
         int q, r;
         item(it, q, r);
         const int t = blk(q);
         if (r < q) {
             const int sb = blk(r);
+            if (direct) {
+                const int a = 64 * t + arow, b0 = 64 * sb + 16 * k4;
+                const int32_t *row = T + (int64_t)(a < d ? a : d - 1) * ldt;
+                if (vec && b0 + KS <= d) {
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const int k = 4 * ks + k4;
-                const int a = direct ? 64 * t + arow : 64 * sb + k, b = direct ? 64 * sb + k : 64 * t + arow;
-                ni[ks] = T[(int64_t)(a < d ? a : d - 1) * ldt + (b < d ? b : d - 1)];
+                    for (int v = 0; v < KS / 4; ++v) {
+                        const uint4 x = *(const uint4 *)(row + b0 + 4 * v);
+                        sl[4 * v] = x.x;
+                        sl[4 * v + 1] = x.y;
+                        sl[4 * v + 2] = x.z;
+                        sl[4 * v + 3] = x.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks) {
+                        const int b = b0 + ks;
+                        sl[ks] = (uint32_t)row[b < d ? b : d - 1];
+                    }
+                }
+            } else {
+                const int b = 64 * t + arow;
+                const int bc = b < d ? b : d - 1;
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    const int a = 64 * sb + 16 * k4 + ks;
+                    sl[ks] = (uint32_t)T[(int64_t)(a < d ? a : d - 1) * ldt + bc];
+                }
             }
         } else {
             const double *Wt = W + (int64_t)t * kTB * kTB;
+            if (LEFT) {
+                const uint4 *w4 = (const uint4 *)(Wt + arow * kTB + 16 * k4);
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const int k = 4 * ks + k4;
-                nd[ks] = LEFT ? Wt[arow * kTB + k] : Wt[k * kTB + arow];
+                for (int v = 0; v < KS / 2; ++v) {
+                    const uint4 x = w4[v];
+                    sl[4 * v] = x.x;
+                    sl[4 * v + 1] = x.y;
+                    sl[4 * v + 2] = x.z;
+                    sl[4 * v + 3] = x.w;
+                }
+            } else {
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    const uint2 x = *(const uint2 *)(Wt + (16 * k4 + ks) * kTB + arow);
+                    sl[2 * ks] = x.x;
+                    sl[2 * ks + 1] = x.y;
+                }
             }
         }
     };
@@ -260,7 +302,7 @@ __global__ __launch_bounds__(256) void k_trsm_blk(int d, int64_t nv, const int32
     auto product = [&](const double (&av)[KS], int row0, v4d &ac) {
         int32_t bv[KS];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) bv[ks] = S[row0 + 4 * ks + k4][r16];
+        for (int ks = 0; ks < KS; ++ks) bv[ks] = S[row0 + 16 * k4 + ks][r16];
         int steps = 0;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
@@ -275,27 +317,30 @@ __global__ __launch_bounds__(256) void k_trsm_blk(int d, int64_t nv, const int32
 #pragma unroll
         for (int v = 0; v < 4; ++v) ac[v] = mod_near(ac[v], p, pinv);
     };
-    prefetch(0);
+#pragma unroll
+    for (int j = 0; j < PD; ++j)
+        if (j < nitems) prefetch(j, ring[j]);
     __syncthreads();
-    for (int it = 0; it < nitems; ++it) {
+    auto run_item = [&](int it, uint32_t(&sl)[2 * KS]) {
         int q, r;
         item(it, q, r);
         const int t = blk(q);
-        // this item's operand (the prefetch registers are refilled below)
+        // this item's operand (its slot is refilled below)
         double av[KS];
         if (r < q) {
             const int sb = blk(r);
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                const bool in = 64 * t + arow < d && 64 * sb + 4 * ks + k4 < d;
-                const int32_t x = in ? ni[ks] : 0;
+                const bool in = 64 * t + arow < d && 64 * sb + 16 * k4 + ks < d;
+                const int32_t x = in ? (int32_t)sl[ks] : 0;
                 av[ks] = x > half ? (double)(x - ip) : (double)x;
             }
         } else {
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) av[ks] = nd[ks];
+            for (int ks = 0; ks < KS; ++ks)
+                av[ks] = __builtin_bit_cast(double, ((uint64_t)sl[2 * ks + 1] << 32) | sl[2 * ks]);
         }
-        prefetch(it + 1);
+        if (it + PD < nitems) prefetch(it + PD, sl);
         if (r < q) {
             product(av, 64 * blk(r), acc);
         } else {
@@ -317,6 +362,15 @@ __global__ __launch_bounds__(256) void k_trsm_blk(int d, int64_t nv, const int32
             for (int v = 0; v < 4; ++v) S[64 * t + 16 * wave + k4 + 4 * v][r16] = (int32_t)cmod(x2[v], p, pinv, hd);
             __syncthreads();
         }
+    };
+    if constexpr (PD == 1) {
+        for (int it = 0; it < nitems; ++it) run_item(it, ring[0]);
+    } else {
+        // fully unrolled (guards, no break) so that every ring slot is a
+        // fixed set of registers
+#pragma unroll
+        for (int it = 0; it < MAXIT; ++it)
+            if (it < nitems) run_item(it, ring[it % PD]);
     }
     // ---- slab out
     for (int idx = tid; idx < kTBB * kVB; idx += 256) {
