@@ -138,13 +138,12 @@ int ffp_flaswp(int dim, int64_t m, int64_t n, int32_t *A, int64_t lda, const int
  *   rrp / crp: device int32 arrays of min(m, n) entries receiving the sorted
  *     row / column rank profile in their first r entries (may be NULL).
  * The host drives the recursion and reads each sub-block's rank back, so
- * the call synchronises with `stream` internally.  Within a recursion node
- * the solve E = C1 U1^-1 (and, in the general recursion, its product) runs
- * on a second stream that the library owns (one per device, default
- * priority, shared by all calls on the device), ordered against `stream`
- * with events; the generic attempt below does so only for leading blocks of
- * 256 or more.  All work is joined back into `stream` before the node's next
- * step.
+ * the call synchronises with `stream` internally.  Within a node of the
+ * general recursion the solve E = C1 U1^-1 and its product run on a second
+ * stream that the library owns (one per device, default priority, shared by
+ * all calls on the device), ordered against `stream` with events and joined
+ * back into it before the node's next step; the generic attempt below runs
+ * on `stream` alone.
  * A first attempt assumes a generic rank profile (all leading minors
  * nonzero: plain block LU, no rank read-backs) on a copy kept in the
  * workspace; a zero pivot restores A and runs the general recursion.  The

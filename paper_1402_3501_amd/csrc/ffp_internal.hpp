@@ -92,6 +92,13 @@ int ftrsm_run(int path, const Field &F, int side, int uplo, int trans, int diag,
 size_t ftrsm_ws(int path, const Field &F, int side, int64_t m, int64_t n);
 // solve with the inverses of the diagonal 64 x 64 blocks of op(T) = T already
 // formed (W: ceil(d / 64) blocks of 64 x 64 centred doubles); alpha = 1
+// the two panel solves D = L^-1 Bd (lower, unit, h x nvd) and E = Be U^-1
+// (upper, nve x h) of a generic block LU node on one stream, each base-case
+// pair in one launch; T is the factored h x h diagonal block, Li / Ui its
+// 64-block inverses
+int ftrsm_pair_gen(int path, const Field &F, int64_t h, const int32_t *T, int64_t ldt, int64_t nvd, int32_t *Bd,
+                   int64_t nve, int32_t *Be, int64_t ldb, const double *Li, const double *Ui, Arena &ws,
+                   hipStream_t s);
 int ftrsm_with_inverses(int path, const Field &F, int side, bool lower, int64_t m, int64_t n,
                         const int32_t *T, int64_t ldt, int32_t *B, int64_t ldb, const double *W, Arena &ws,
                         hipStream_t s);

@@ -85,13 +85,13 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // multiplied on the FP64 matrix cores (4 waves, 32 x 32 each) and written
 // back; slabs of different workgroups are disjoint.
 template <bool LEFT, bool RED>
-__global__ __launch_bounds__(256) void k_trsm_apply(int db, int64_t nv, const double *__restrict__ W,
-                                                    int32_t *__restrict__ B, int64_t ldb, double p, double pinv,
-                                                    int32_t half, int ksteps) {
+__device__ __forceinline__ void trsm_apply_body(int bid, int db, int64_t nv, const double *__restrict__ W,
+                                                int32_t *__restrict__ B, int64_t ldb, double p, double pinv,
+                                                int32_t half, int ksteps) {
     __shared__ double Ws[kTB][kTB + 2];
     __shared__ int32_t Ss[kTB][kTB + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t v0 = (int64_t)blockIdx.x * kTB;
+    const int64_t v0 = (int64_t)bid * kTB;
     {
         constexpr int PER = kTB * kTB / 256;
         double w[PER];
@@ -168,6 +168,13 @@ __global__ __launch_bounds__(256) void k_trsm_apply(int db, int64_t nv, const do
             }
 }
 
+template <bool LEFT, bool RED>
+__global__ __launch_bounds__(256) void k_trsm_apply(int db, int64_t nv, const double *__restrict__ W,
+                                                    int32_t *__restrict__ B, int64_t ldb, double p, double pinv,
+                                                    int32_t half, int ksteps) {
+    trsm_apply_body<LEFT, RED>(blockIdx.x, db, nv, W, B, ldb, p, pinv, half, ksteps);
+}
+
 constexpr int kTBB = 256;  // fused base case: up to four 64-blocks
 
 // Fused base case for triangles of up to 256: one workgroup per 16 vectors
@@ -189,15 +196,15 @@ constexpr int kTBB = 256;  // fused base case: up to four 64-blocks
 constexpr int kVB = 16;  // vectors per workgroup of the fused base case
 
 template <bool LEFT, bool RED>
-__global__ __launch_bounds__(256) void k_trsm_blk(int d, int64_t nv, const int32_t *__restrict__ T, int64_t ldt,
-                                                  int direct, int fwd, const double *__restrict__ W,
-                                                  int32_t *__restrict__ B, int64_t ldb, double p, double pinv,
-                                                  int32_t half, int ksteps) {
+__device__ __forceinline__ void trsm_blk_body(int bid, int d, int64_t nv, const int32_t *__restrict__ T,
+                                              int64_t ldt, int direct, int fwd, const double *__restrict__ W,
+                                              int32_t *__restrict__ B, int64_t ldb, double p, double pinv,
+                                              int32_t half, int ksteps) {
     constexpr int KS = kTB / 4;           // k-steps per 64 x 16 x 64 product
     __shared__ int32_t S[kTBB][kVB + 1];  // [component][vector]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, k4 = lane >> 4;
-    const int64_t v0 = (int64_t)blockIdx.x * kVB;
+    const int64_t v0 = (int64_t)bid * kVB;
     const int nb = (d + kTB - 1) / kTB;
     const double hd = (double)half;
     const int32_t ip = (int32_t)p;
@@ -384,6 +391,37 @@ __global__ __launch_bounds__(256) void k_trsm_blk(int d, int64_t nv, const int32
     }
 }
 
+template <bool LEFT, bool RED>
+__global__ __launch_bounds__(256) void k_trsm_blk(int d, int64_t nv, const int32_t *__restrict__ T, int64_t ldt,
+                                                  int direct, int fwd, const double *__restrict__ W,
+                                                  int32_t *__restrict__ B, int64_t ldb, double p, double pinv,
+                                                  int32_t half, int ksteps) {
+    trsm_blk_body<LEFT, RED>(blockIdx.x, d, nv, T, ldt, direct, fwd, W, B, ldb, p, pinv, half, ksteps);
+}
+
+// The two panel solves of a generic block LU node in one launch, for a
+// leading block of h <= 256 (one base case each): D = L^-1 B (left, lower,
+// forward) on the first gd workgroups and E = C U^-1 (right, upper, forward)
+// on the rest; they read the same diagonal block and write disjoint panels.
+template <bool RED>
+__global__ __launch_bounds__(256) void k_trsm_apply_pair(int h, int gd, int64_t nvd, int32_t *__restrict__ Bd,
+                                                         int64_t nve, int32_t *__restrict__ Be, int64_t ldb,
+                                                         const double *__restrict__ Li,
+                                                         const double *__restrict__ Ui, double p, double pinv,
+                                                         int32_t half, int ksteps) {
+    if ((int)blockIdx.x < gd) trsm_apply_body<true, RED>(blockIdx.x, h, nvd, Li, Bd, ldb, p, pinv, half, ksteps);
+    else trsm_apply_body<false, RED>(blockIdx.x - gd, h, nve, Ui, Be, ldb, p, pinv, half, ksteps);
+}
+template <bool RED>
+__global__ __launch_bounds__(256) void k_trsm_blk_pair(int h, int gd, int64_t nvd, int32_t *__restrict__ Bd,
+                                                       int64_t nve, int32_t *__restrict__ Be, int64_t ldb,
+                                                       const int32_t *__restrict__ T, int64_t ldt,
+                                                       const double *__restrict__ Li, const double *__restrict__ Ui,
+                                                       double p, double pinv, int32_t half, int ksteps) {
+    if ((int)blockIdx.x < gd) trsm_blk_body<true, RED>(blockIdx.x, h, nvd, T, ldt, 1, 1, Li, Bd, ldb, p, pinv, half, ksteps);
+    else trsm_blk_body<false, RED>(blockIdx.x - gd, h, nve, T, ldt, 0, 1, Ui, Be, ldb, p, pinv, half, ksteps);
+}
+
 static int trsm_blk(const Field &F, int side, int d, int64_t nv, const int32_t *T, int64_t ldt, bool direct,
                     bool fwd, const double *W, int32_t *B, int64_t ldb, hipStream_t s) {
     if (d <= 0 || nv <= 0) return FFP_OK;
@@ -513,6 +551,54 @@ int ftrsm_with_inverses(int path, const Field &F, int side, bool lower, int64_t 
     if (m <= 0 || n <= 0) return FFP_OK;
     const int64_t d = side == 0 ? m : n, nv = side == 0 ? n : m;
     return trsm_rec(path, F, side, lower, 0, d, nv, T, ldt, B, ldb, W, ws, s);
+}
+
+static int trsm_pair_base(const Field &F, int64_t h, const int32_t *T, int64_t ldt, int64_t nvd, int32_t *Bd,
+                          int64_t nve, int32_t *Be, int64_t ldb, const double *Li, const double *Ui, hipStream_t s) {
+    if (h <= 0 || h > kTBB || (nvd <= 0 && nve <= 0)) return FFP_OK;
+    const int ksteps = (int)(F.kexact / 4 < 1 ? 1 : (F.kexact / 4 > 16 ? 16 : F.kexact / 4));
+    if (h <= kTB) {
+        const bool red = F.kexact < h;
+        const int gd = (int)((nvd + kTB - 1) / kTB), ge = (int)((nve + kTB - 1) / kTB);
+#define FFP_AP(R_)                                                                                          \
+    hipLaunchKernelGGL((k_trsm_apply_pair<R_>), dim3((unsigned)(gd + ge)), dim3(256), 0, s, (int)h, gd, nvd, Bd, \
+                       nve, Be, ldb, Li, Ui, F.pd, F.pinv, (int32_t)F.half, ksteps)
+        if (red) FFP_AP(true);
+        else FFP_AP(false);
+#undef FFP_AP
+    } else {
+        const bool red = F.kexact < kTB;
+        const int gd = (int)((nvd + kVB - 1) / kVB), ge = (int)((nve + kVB - 1) / kVB);
+#define FFP_BP(R_)                                                                                          \
+    hipLaunchKernelGGL((k_trsm_blk_pair<R_>), dim3((unsigned)(gd + ge)), dim3(256), 0, s, (int)h, gd, nvd, Bd, nve, \
+                       Be, ldb, T, ldt, Li, Ui, F.pd, F.pinv, (int32_t)F.half, ksteps)
+        if (red) FFP_BP(true);
+        else FFP_BP(false);
+#undef FFP_BP
+    }
+    FFP_HIP_CHECK(hipGetLastError());
+    return FFP_OK;
+}
+
+// Both solves recurse in step (forward, the same 256-multiple splits): each
+// level's two base cases share one launch, and the two products between them
+// run back to back on the same stream.
+int ftrsm_pair_gen(int path, const Field &F, int64_t h, const int32_t *T, int64_t ldt, int64_t nvd, int32_t *Bd,
+                   int64_t nve, int32_t *Be, int64_t ldb, const double *Li, const double *Ui, Arena &ws,
+                   hipStream_t s) {
+    if (h <= 0 || (nvd <= 0 && nve <= 0)) return FFP_OK;
+    if (h <= kTBB) return trsm_pair_base(F, h, T, ldt, nvd, Bd, nve, Be, ldb, Li, Ui, s);
+    const uint32_t minus1 = F.p - 1;
+    const int64_t d1 = ((h / 2 + kTBB - 1) / kTBB) * kTBB < h ? ((h / 2 + kTBB - 1) / kTBB) * kTBB : kTBB;
+    const int64_t d2 = h - d1, off = (d1 / kTB) * kTB * kTB;
+    FFP_CHECK(ftrsm_pair_gen(path, F, d1, T, ldt, nvd, Bd, nve, Be, ldb, Li, Ui, ws, s));
+    // D2 -= L21 D1 (rows d1.. of the left panel), E2 -= E1 U12 (columns d1.. of the right one)
+    if (nvd > 0)
+        FFP_CHECK(fgemm_any(path, F, 0, 0, d2, nvd, d1, minus1, T + d1 * ldt, ldt, Bd, ldb, 1, Bd + d1 * ldb, ldb, ws, s));
+    if (nve > 0)
+        FFP_CHECK(fgemm_any(path, F, 0, 0, nve, d2, d1, minus1, Be, ldb, T + d1, ldt, 1, Be + d1, ldb, ws, s));
+    return ftrsm_pair_gen(path, F, d2, T + d1 * ldt + d1, ldt, nvd, Bd + d1 * ldb, nve, Be + d1, ldb, Li + off,
+                          Ui + off, ws, s);
 }
 
 size_t ftrsm_ws(int path, const Field &F, int side, int64_t m, int64_t n) {
