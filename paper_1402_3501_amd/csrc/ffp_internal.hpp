@@ -135,9 +135,15 @@ int copy2d(int64_t m, int64_t n, const int32_t *src, int64_t lds, int32_t *dst, 
 // PLUQ leaf for blocks of at most 64 x 64 (one wave; rank to rank_dev); with
 // gflag non-null: plain LU leaf of the generic-rank-profile attempt (a zero
 // pivot sets *gflag; P, Q and rank are not written; with Linv / Uinv
-// non-null, the 64 x 64 inverses of its L and U blocks are stored there)
+// non-null, the 64 x 64 inverses of its L and U blocks are stored there).
+// Generic leaf only, when 64-term sums need no reduction: He / Hd first
+// update the block, A <- A - He Hd (He: m x 64, Hd: 64 x n, leading
+// dimension lda); Pd / Pe (a full 64 x 64 block with inverses) are replaced
+// after it by L^-1 Pd (64 x pdn) and Pe U^-1 (pem x 64).
 int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
-                  int64_t *rank_dev, int *gflag, double *Linv, double *Uinv, hipStream_t s);
+                  int64_t *rank_dev, int *gflag, double *Linv, double *Uinv, hipStream_t s,
+                  const int32_t *He = nullptr, const int32_t *Hd = nullptr, int32_t *Pd = nullptr,
+                  int64_t pdn = 0, int32_t *Pe = nullptr, int64_t pem = 0);
 
 // PLUQ (host recursion); P, Q device outputs (local indices); returns rank via *r
 int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P,

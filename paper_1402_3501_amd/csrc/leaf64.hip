@@ -300,11 +300,20 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
 // With Linv / Uinv non-null the leaf also stores L^-1 and U^-1 of its k x k
 // diagonal block (k = min(mb, nb); 64 x 64 centred doubles, zero outside),
 // the base-case inverses of later triangular solves with these blocks.
+// Fused neighbours (generic node of at most 128 x 128 whose two halves are
+// leaves; host ensures 64 x (p/2)^2 sums are exact, i.e. no reduction):
+//  - He / Hd non-null: the block is first updated, A <- A - He Hd, with He
+//    the mb x 64 and Hd the 64 x nb operand (leading dimension lda);
+//  - Pd / Pe non-null (needs Linv): after the factorisation the 64 x pdn
+//    panel right of the block becomes L^-1 Pd and the pem x 64 panel below
+//    it Pe U^-1 (the two solves of the node).
 template <bool SMALLP, int NW>
 __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *__restrict__ A, int64_t lda,
                                                       double p, double pinv, int32_t half, int *__restrict__ gflag,
                                                       double *__restrict__ Linv, double *__restrict__ Uinv,
-                                                      int inv_red, int kchunk) {
+                                                      int inv_red, int kchunk, const int32_t *__restrict__ He,
+                                                      const int32_t *__restrict__ Hd, int32_t *__restrict__ Pd,
+                                                      int pdn, int32_t *__restrict__ Pe, int pem) {
     static_assert(NW == 8, "four pivot rows per block share one row slot; two 256-thread inversion groups");
     constexpr int RPW = 64 / NW;  // rows per wave
     constexpr int KB = 4;         // elimination steps per barrier
@@ -339,6 +348,41 @@ __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *_
         }
     }
     const int kd = mb < nb ? mb : nb;
+    if (He) {
+        // H = He Hd on the matrix cores, wave w: output tiles (w % 4, 2 (w / 4) + t);
+        // reduction index 16 (lane / 16) + s at k-step s, as for every operand here
+        const int tr = wave & 3, tcb = 2 * (wave >> 2), r16 = lane & 15, kq = lane >> 4;
+        int32_t ev[16], dv[2][16];
+#pragma unroll
+        for (int sidx = 0; sidx < 16; ++sidx) {
+            const int k = 16 * kq + sidx, i = 16 * tr + r16;
+            ev[sidx] = He[(int64_t)(i < mb ? i : 0) * lda + k];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int c = 16 * (tcb + t) + r16;
+                dv[t][sidx] = Hd[(int64_t)k * lda + (c < nb ? c : 0)];
+            }
+        }
+        v4d_t acc[2] = {v4d_t{0.0, 0.0, 0.0, 0.0}, v4d_t{0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+        for (int sidx = 0; sidx < 16; ++sidx) {
+            const double a = centre(ev[sidx], p, half);
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, centre(dv[t][sidx], p, half), acc[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sh.v.Ws[0][16 * tr + kq + 4 * v][16 * (tcb + t) + r16] = acc[t][v];
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < RPW; ++e) {
+            const int i = wave + NW * e;
+            if (i < mb && lane < nb) R[e] = mod_near(R[e] - sh.v.Ws[0][i][lane], p, pinv);
+        }
+        __syncthreads();  // the staging area is the pivot-row buffer below
+    }
     // one fraction-free step on a row x held lane-wise: pivot row um (zero in
     // columns <= k), pivot q, step k.  Columns <= k are multiplied by q
     // instead of being left alone (no select); the final scaling divides the
@@ -375,7 +419,12 @@ __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *_
             if (tid == 0) *gflag = 1;
             return;
         }
-        if (tid < nbk) qv[kb + tid] = tid == 0 ? q[0] : tid == 1 ? q[1] : tid == 2 ? q[2] : q[3];
+        if (tid < nbk) {
+            double qt = q[0];
+#pragma unroll
+            for (int j = 1; j < KB; ++j) qt = tid == j ? q[j] : qt;
+            qv[kb + tid] = qt;
+        }
         // own rows: below the block, KB steps; in the block, the final pivot row
 #pragma unroll
         for (int e = eb; e < RPW; ++e) {
@@ -383,7 +432,10 @@ __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *_
             const bool below = e > eb || wave >= w0 + nbk;  // rows after the block's pivots
             if (inblk) {
                 const int j = wave - w0;
-                R[e] = j == 0 ? u[0] : j == 1 ? u[1] : j == 2 ? u[2] : u[3];
+                double ut = u[0];
+#pragma unroll
+                for (int jj = 1; jj < KB; ++jj) ut = j == jj ? u[jj] : ut;
+                R[e] = ut;
             } else if (below) {
                 double x = R[e];
 #pragma unroll
@@ -467,12 +519,57 @@ __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *_
         Linv[idx] = in ? sh.v.Ws[0][i][j] : 0.0;
         Uinv[idx] = in ? sh.v.Ws[1][j][i] : 0.0;
     }
+    if (Pd) {
+        // D = L^-1 Pd (64 x pdn) and E = Pe U^-1 (pem x 64), in place: every
+        // wave reads its operands, then all write (tiles share source rows
+        // and columns)
+        __syncthreads();
+        const int tr = wave & 3, tcb = 2 * (wave >> 2), r16 = lane & 15, kq = lane >> 4;
+        v4d_t accd[2] = {v4d_t{0.0, 0.0, 0.0, 0.0}, v4d_t{0.0, 0.0, 0.0, 0.0}};
+        v4d_t acce[2] = {v4d_t{0.0, 0.0, 0.0, 0.0}, v4d_t{0.0, 0.0, 0.0, 0.0}};
+        {
+            int32_t bv[2][16], cv[16];
+#pragma unroll
+            for (int sidx = 0; sidx < 16; ++sidx) {
+                const int k = 16 * kq + sidx, i = 16 * tr + r16;
+                cv[sidx] = Pe[(int64_t)(i < pem ? i : 0) * lda + k];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int c = 16 * (tcb + t) + r16;
+                    bv[t][sidx] = Pd[(int64_t)k * lda + (c < pdn ? c : 0)];
+                }
+            }
+#pragma unroll
+            for (int sidx = 0; sidx < 16; ++sidx) {
+                const int k = 16 * kq + sidx;
+                const double li = sh.v.Ws[0][16 * tr + r16][k];
+                const double ce = centre(cv[sidx], p, half);
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    // U^-1[k][c] = (U^T)^-1[c][k]
+                    const double ui = sh.v.Ws[1][16 * (tcb + t) + r16][k];
+                    accd[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(li, centre(bv[t][sidx], p, half), accd[t], 0, 0, 0);
+                    acce[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ce, ui, acce[t], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * tr + kq + 4 * v, c = 16 * (tcb + t) + r16;
+                if (c < pdn) Pd[(int64_t)i * lda + c] = (int32_t)mod_canon(accd[t][v], p, pinv);
+                if (i < pem) Pe[(int64_t)i * lda + c] = (int32_t)mod_canon(acce[t][v], p, pinv);
+            }
+    }
 }
 
 constexpr int kGenWaves = 8;
 
 int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
-                  int64_t *rank_dev, int *gflag, double *Linv, double *Uinv, hipStream_t s) {
+                  int64_t *rank_dev, int *gflag, double *Linv, double *Uinv, hipStream_t s, const int32_t *He,
+                  const int32_t *Hd, int32_t *Pd, int64_t pdn, int32_t *Pe, int64_t pem) {
     const bool red = F.kexact < 64;
     const bool small = F.p < (1u << 24);
 #define FFP_L64(R_, S_)                                                                                    \
@@ -488,10 +585,16 @@ int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda,
         // dot products of the block inversion take at most 32 terms
         const int inv_red = F.kexact < 32;
         const int kchunk = (int)(F.kexact < 1 ? 1 : (F.kexact > 32 ? 32 : F.kexact));
+        // the fused products sum 64 terms unreduced
+        if ((He || Pd) && (F.kexact < 64 || (Pd && (!Linv || m != 64 || n != 64 || pdn > 64 || pem > 64)) ||
+                           (He && (!Hd || m > 64 || n > 64))))
+            return FFP_E_INTERNAL;
         if (small) hipLaunchKernelGGL((k_leaf_gen<true, kGenWaves>), dim3(1), dim3(64 * kGenWaves), 0, s, (int)m, (int)n, A,
-                                      lda, F.pd, F.pinv, (int32_t)F.half, gflag, Linv, Uinv, inv_red, kchunk);
+                                      lda, F.pd, F.pinv, (int32_t)F.half, gflag, Linv, Uinv, inv_red, kchunk, He, Hd,
+                                      Pd, (int)pdn, Pe, (int)pem);
         else hipLaunchKernelGGL((k_leaf_gen<false, kGenWaves>), dim3(1), dim3(64 * kGenWaves), 0, s, (int)m, (int)n, A,
-                                lda, F.pd, F.pinv, (int32_t)F.half, gflag, Linv, Uinv, inv_red, kchunk);
+                                lda, F.pd, F.pinv, (int32_t)F.half, gflag, Linv, Uinv, inv_red, kchunk, He, Hd, Pd,
+                                (int)pdn, Pe, (int)pem);
     } else {
         FFP_SEL(FFP_L64)
     }

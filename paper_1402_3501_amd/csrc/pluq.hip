@@ -697,6 +697,14 @@ int lu_generic(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int *gflag
     if (leaf64_fits(m, n)) return leaf64_launch(*c.F, m, n, A, lda, nullptr, nullptr, nullptr, gflag, Li, Ui, c.s);
     const int64_t k = m < n ? m : n;
     const int64_t h = k <= 64 ? k : 64 * ((k + 127) / 128);
+    if (h == 64 && m <= 128 && n <= 128 && c.F->kexact >= 64) {
+        // both halves are leaves: the node's two solves run at the end of the
+        // first leaf and its update H = A4 - E D at the start of the second
+        FFP_CHECK(leaf64_launch(*c.F, 64, 64, A, lda, nullptr, nullptr, nullptr, gflag, Li, Ui, c.s, nullptr,
+                                nullptr, A + 64, n - 64, A + 64 * lda, m - 64));
+        return leaf64_launch(*c.F, m - 64, n - 64, A + 64 * lda + 64, lda, nullptr, nullptr, nullptr, gflag,
+                             Li + kBlk, Ui + kBlk, c.s, A + 64 * lda, A + 64);
+    }
     FFP_CHECK(lu_generic(c, h, h, A, lda, gflag, Li, Ui));
     FFP_CHECK(node_updates_gen(c, m, n, h, A, lda, Li, Ui));
     const int64_t off = (h / 64) * kBlk;  // h is a multiple of 64 whenever the rest is non-empty
