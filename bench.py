@@ -9,7 +9,10 @@ about 0.1% of the step.  value = (2 n^3 / 3) / step time, the paper's
 effective rate.
 
 Also printed (outside the timed steps): the same PLUQ on the other path,
-the 8192^3 fgemm on both paths, and bit-exact agreement between paths.
+the 8192^3 fgemm on both paths, and bit-exact agreement between paths; the
+rank-deficient 8192 workload (rank 4096); PLUQ and the n^3 product at
+n = 16384 mod 251 (one INT8 limb) and mod 8388593 (three limbs) on both
+paths with bit-exact agreement; the batched workload.
 
 The roofline object is for the dominant contraction kernel (the modular
 matrix product family with the most time in the step), from HIP events that
@@ -214,6 +217,67 @@ def main():
         if len(results) == 2:
             extra["fgemm_paths_bit_exact"] = bool(torch.equal(results["fp64"], results["int8"]))
         del X, Y, results
+        # the other single-matrix workloads: rank-deficient 8192 (rank 4096,
+        # rank-deficient pivot blocks), and n = 16384 with one limb (p = 251)
+        # and three limbs (p = 8388593), each PLUQ and n^3 product on both
+        # paths with bit-exact agreement
+        def timed(fn, reps=1):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                r_ = fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3 / reps, r_
+
+        def pluq_on(name, pth):
+            spec2 = wl.WORKLOADS[name]
+            mm2, nn2, p2 = spec2["m"], spec2["n"], spec2["p"]
+            B0 = torch.from_numpy(wl.make(name)).to(dev)
+            B = torch.empty_like(B0)
+            P2 = torch.empty(mm2, dtype=torch.int32, device=dev)
+            Q2 = torch.empty(nn2, dtype=torch.int32, device=dev)
+            k2 = min(mm2, nn2)
+            rp2 = torch.empty(k2, dtype=torch.int32, device=dev)
+            cp2 = torch.empty(k2, dtype=torch.int32, device=dev)
+            rd2 = torch.empty(1, dtype=torch.int64, device=dev)
+            ws3 = torch.empty(ffp.pluq_workspace(mm2, nn2, p2, pth), dtype=torch.uint8, device=dev)
+
+            def run():
+                B.copy_(B0)
+                return ffp.pluq_into(B, p2, P2, Q2, rd2, rp2, cp2, ws3, path=pth)
+            t, rk = timed(run)
+            return t, rk, (B.clone(), P2.clone(), Q2.clone())
+
+        log("[bench] rank-deficient 8192 ...")
+        t, rk, _ = pluq_on("pluq8192_r4096_p131071", ffp.PATH_AUTO)
+        extra["pluq8192_r4096_ms"] = round(t, 3)
+        extra["pluq8192_r4096_rank"] = rk
+        extra["pluq8192_r4096_algorithmic_gops"] = round(
+            (2.0 * 8192 * 8192 * rk - 2 * 8192 * rk * rk + 2.0 * rk ** 3 / 3) / (t * 1e-3) / 1e9, 3)
+        for name in ("n16384_p251", "n16384_p8388593"):
+            log(f"[bench] {name} ...")
+            p2 = wl.WORKLOADS[name]["p"]
+            n2 = wl.WORKLOADS[name]["n"]
+            outs = {}
+            for pth, pn in ((ffp.PATH_INT8, "int8"), (ffp.PATH_FP64, "fp64")):
+                t, rk, o = pluq_on(name, pth)
+                extra[f"{name}_pluq_{pn}_ms"] = round(t, 3)
+                extra[f"{name}_pluq_{pn}_gops"] = round(2.0 * n2 ** 3 / 3 / (t * 1e-3) / 1e9, 3)
+                outs[pn] = o
+            extra[f"{name}_pluq_paths_bit_exact"] = all(torch.equal(a, b) for a, b in zip(outs["int8"], outs["fp64"]))
+            del outs
+            X = torch.from_numpy(wl.uniform(n2, n2, p2, 202)).to(dev)
+            Y = torch.from_numpy(wl.uniform(n2, n2, p2, 203)).to(dev)
+            zs = {}
+            for pth, pn in ((ffp.PATH_INT8, "int8"), (ffp.PATH_FP64, "fp64")):
+                Z = torch.zeros((n2, n2), dtype=torch.int32, device=dev)
+                t, _ = timed(lambda: ffp.fgemm(X, Y, Z, p2, path=pth), reps=2)
+                extra[f"{name}_fgemm_{pn}_ms"] = round(t, 3)
+                extra[f"{name}_fgemm_{pn}_gops"] = round(2.0 * n2 ** 3 / (t * 1e-3) / 1e9, 3)
+                zs[pn] = Z
+            extra[f"{name}_fgemm_paths_bit_exact"] = bool(torch.equal(zs["int8"], zs["fp64"]))
+            del X, Y, zs
         # the batched persistent PLUQ on its own workload (4096 matrices,
         # m, n uniform in [16, 512], ranks uniform in [1, min]); ranks checked
         log("[bench] batched workload ...")

@@ -277,6 +277,24 @@ def pluq_batched(ms, ns, A_packed, A_off, p: int, path: int = PATH_AUTO, max_m: 
     return BatchedResult(P, Q, rank[:batch], rrp, crp)
 
 
+def pluq_batched_into(ms, ns, max_m: int, max_n: int, A_packed, A_off, P, P_off, Q, Q_off, rank, rrp, crp,
+                      ws, p: int, path: int = PATH_AUTO) -> None:
+    """The batched factorisation into caller-provided outputs and workspace:
+    no allocation and no host synchronisation (two kernel launches on the
+    current stream), so the call can be captured in a graph."""
+    torch = _torch()
+    lib = load()
+    batch = int(ms.numel())
+    _check(lib.ffp_pluq_batched(batch, _vec(ms, "ms"), _vec(ns, "ns"), max_m, max_n, p,
+                                _vec(A_packed, "A_packed"), _vec(A_off, "A_off", torch.int64),
+                                _vec(P, "P"), _vec(P_off, "P_off", torch.int64), _vec(Q, "Q"),
+                                _vec(Q_off, "Q_off", torch.int64), _vec(rank, "rank"),
+                                _vec(rrp, "rrp") if rrp is not None else None,
+                                _vec(crp, "crp") if crp is not None else None, path,
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(A_packed)),
+           "ffp_pluq_batched")
+
+
 def perm_to_swaps(perm) -> np.ndarray:
     perm = np.ascontiguousarray(perm, np.int32)
     ipiv = np.zeros(max(len(perm), 1), np.int32)

@@ -145,6 +145,33 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
     uint64_t f_rows = lane == 0 ? allr : 0, f_cols = lane == 0 ? allc : 0, f_top = 0, f_left = 0;
     int f_stage = 0;
     int sp = generic ? 0 : 1;
+    // nonzero entries of the active block, one row mask per column (lane);
+    // the block changes only at a pivot, so the masks are rebuilt at most
+    // once per pivot, when the walk next asks.  A region of the walk holds a
+    // pivot exactly when it holds a nonzero entry: zero regions (the whole
+    // rest of a rank-deficient block, typically) are skipped with one ballot
+    // instead of being walked down to their one-row / one-column pieces.
+    uint64_t nzm = 0;
+    bool nz_valid = false;
+    auto region_nz = [&](uint64_t rows, uint64_t cols) {
+        if (!nz_valid) {
+            uint64_t mk = 0;
+            if (lane < nb && !((coldone >> lane) & 1ull)) {
+#pragma unroll
+                for (int g = 0; g < 64; g += 32) {
+                    double wv[32];
+#pragma unroll
+                    for (int q = 0; q < 32; ++q) wv[q] = W[g + q][lane];
+#pragma unroll
+                    for (int q = 0; q < 32; ++q)
+                        if (mod_canon(wv[q], p, pinv) != 0.0) mk |= 1ull << (g + q);
+                }
+            }
+            nzm = mk & allr & ~rowdone;
+            nz_valid = true;
+        }
+        return __ballot(((cols >> lane) & 1ull) && (nzm & rows) != 0) != 0;
+    };
 
     while (true) {
         // ---- walk the quadrant recursion to the next one-row / one-column region
@@ -155,6 +182,7 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
             const uint64_t rows = rl64(f_rows, t), cols = rl64(f_cols, t);
             const int stage = __builtin_amdgcn_readlane(f_stage, t);
             if (stage == 0) {
+                if (!region_nz(rows, cols)) { --sp; continue; }
                 const int nr = __popcll(rows), nc = __popcll(cols);
                 if (nr == 1) { type = B_ROW; bx = __ffsll((long long)rows) - 1; bmask = cols; --sp; break; }
                 if (nc == 1) { type = B_COL; bx = __ffsll((long long)cols) - 1; bmask = rows; --sp; break; }
@@ -172,7 +200,7 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
                 if (st == 1) { cr = top & ~rowdone; cc = cols & ~left; }
                 else if (st == 2) { cr = rows & ~top; cc = left & ~coldone; }
                 else { cr = rows & ~top & ~rowdone; cc = cols & ~left & ~coldone; }
-                if (cr && cc) {
+                if (cr && cc && region_nz(cr, cc)) {
                     if (lane == t) f_stage = st + 1;
                     if (lane == t + 1) { f_rows = cr; f_cols = cc; f_stage = 0; }
                     ++sp;
@@ -259,6 +287,7 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
         rowdone |= 1ull << x;
         coldone |= 1ull << y;
         ++r;
+        nz_valid = false;
         __syncthreads();
     }
 

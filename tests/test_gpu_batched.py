@@ -101,3 +101,67 @@ def test_batched_workload_4096(lib, orc):
         err = checks.full_check(Ai, LU[off[i]:off[i] + m * n].reshape(m, n), P[po[i]:po[i] + m],
                                 Q[qo[i]:qo[i] + n], int(rank[i]), p, orc.order, exact_limit=0)
         assert err is None, (i, err)
+
+
+def test_batched_graph_capture_replays(lib, orc):
+    """The batched call captured in a HIP graph (two kernel launches, no host
+    synchronisation, no allocation): three replays, each after eager work and
+    a synchronisation, each equal to the eager result bit for bit; a sample
+    of matrices also against the oracle."""
+    import torch
+    p = 65521
+    ms, ns, rs, A, off = wl.batch(192, 16, 160, p, 77)
+    dev = "cuda"
+    msd = torch.from_numpy(ms.astype(np.int32)).to(dev)
+    nsd = torch.from_numpy(ns.astype(np.int32)).to(dev)
+    offd = torch.from_numpy(off.astype(np.int64)).to(dev)
+    A0 = torch.from_numpy(A.astype(np.int32)).to(dev)
+    note("batched graph: eager reference")
+    Ae = A0.clone()
+    ref = lib.pluq_batched(msd, nsd, Ae, offd, p)
+    torch.cuda.synchronize()
+    max_m, max_n = int(ms.max()), int(ns.max())
+    tm, tn, batch = int(ms.sum()), int(ns.sum()), len(ms)
+    po = torch.from_numpy(np.concatenate([[0], np.cumsum(ms)[:-1]]).astype(np.int64)).to(dev)
+    qo = torch.from_numpy(np.concatenate([[0], np.cumsum(ns)[:-1]]).astype(np.int64)).to(dev)
+    P = torch.empty(tm, dtype=torch.int32, device=dev)
+    Q = torch.empty(tn, dtype=torch.int32, device=dev)
+    rrp = torch.empty(tm, dtype=torch.int32, device=dev)
+    crp = torch.empty(tn, dtype=torch.int32, device=dev)
+    rank = torch.empty(batch, dtype=torch.int32, device=dev)
+    ws = torch.empty(lib.load().ffp_pluq_batched_workspace(batch, max_m, max_n, p, 0), dtype=torch.uint8,
+                     device=dev)
+    Aw = A0.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        # one eager run on the capture stream's side before capturing
+        lib.pluq_batched_into(msd, nsd, max_m, max_n, Aw, offd, P, po, Q, qo, rank, rrp, crp, ws, p)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    note("batched graph: capture")
+    with torch.cuda.graph(g):
+        Aw.copy_(A0)
+        lib.pluq_batched_into(msd, nsd, max_m, max_n, Aw, offd, P, po, Q, qo, rank, rrp, crp, ws, p)
+    for rep in range(3):
+        # eager work between replays: clobber the outputs
+        Aw.fill_(7)
+        P.fill_(-1)
+        Q.fill_(-1)
+        rank.fill_(-1)
+        torch.cuda.synchronize()
+        note(f"batched graph: replay {rep}")
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Aw, Ae), rep
+        assert torch.equal(P, ref.P[:tm]) and torch.equal(Q, ref.Q[:tn]), rep
+        assert torch.equal(rank, ref.rank[:batch]), rep
+        for i in range(batch):
+            r = int(rank[i])
+            a, b = int(po[i]), int(qo[i])
+            assert torch.equal(rrp[a:a + r], ref.rrp[a:a + r]) and torch.equal(crp[b:b + r], ref.crp[b:b + r])
+    assert np.array_equal(rank.cpu().numpy(), rs)
+    out = (Aw.cpu().numpy(), P.cpu().numpy(), Q.cpu().numpy(), rank.cpu().numpy(), rrp.cpu().numpy(),
+           crp.cpu().numpy())
+    _compare(orc, ms, ns, A, off, p, out, range(0, batch, 12))
