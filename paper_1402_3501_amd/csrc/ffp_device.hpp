@@ -93,4 +93,23 @@ __device__ __forceinline__ int32_t inv_mod_uniform(int32_t a, int32_t p) {
     return s0 < 0 ? s0 + p : s0;
 }
 
+// Tile order (one-dimensional grid of ntx x nty tiles): workgroup b runs on
+// XCD b % 8 (the dispatcher deals workgroups round robin over the eight
+// XCDs, each with its own L2), so when nty is a multiple of 8 each XCD gets
+// a band of nty / 8 tile rows, walked four tile rows at a time: the tiles an
+// XCD runs together share A row panels and B column panels in its L2.
+__device__ __forceinline__ void xcd_tile(int b, int ntx, int nty, int &ty, int &tx) {
+    if (nty % 8 != 0) {
+        ty = b / ntx;
+        tx = b % ntx;
+        return;
+    }
+    constexpr int GM = 4;
+    const int xcd = b & 7, loc = b >> 3, band = nty / 8;
+    const int g = loc / (GM * ntx), in = loc % (GM * ntx);
+    const int rows = band - g * GM < GM ? band - g * GM : GM;
+    ty = xcd * band + g * GM + in % rows;
+    tx = in / rows;
+}
+
 }  // namespace ffp

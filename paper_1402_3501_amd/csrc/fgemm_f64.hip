@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void k_fgemm_f64(int64_t m, int64_t n, int64_t
                                                    const int32_t *__restrict__ B, int64_t ldb,
                                                    int32_t *__restrict__ C, int64_t ldc, double p,
                                                    double pinv, int32_t half, double alpha,
-                                                   double beta, int kchunk_steps) {
+                                                   double beta, int kchunk_steps, int ntx, int nty) {
     constexpr int BK = 16;
     constexpr int PAD = 2;
     constexpr int WM = BM / 2, WN = BN / 2;
@@ -38,7 +38,9 @@ __global__ __launch_bounds__(256) void k_fgemm_f64(int64_t m, int64_t n, int64_t
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
-    const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+    int ty, tx;
+    xcd_tile(blockIdx.x, ntx, nty, ty, tx);
+    const int64_t m0 = (int64_t)ty * BM, n0 = (int64_t)tx * BN;
 
     int32_t ra[A_PER], rb[B_PER];
 
@@ -444,9 +446,11 @@ static void launch_tiles(int ta, int tb, dim3 grid, hipStream_t s, int64_t m, in
                          const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, int32_t *C,
                          int64_t ldc, double p, double pinv, int32_t half, double alpha,
                          double beta, int ksteps) {
+    const int ntx = (int)grid.x, nty = (int)grid.y;
+    const dim3 g1((unsigned)(ntx * nty));
 #define FFP_LAUNCH(TA_, TB_)                                                                  \
-    hipLaunchKernelGGL((k_fgemm_f64<BM, BN, TA_, TB_, RED>), grid, dim3(256), 0, s, m, n, k, A, \
-                       lda, B, ldb, C, ldc, p, pinv, half, alpha, beta, ksteps)
+    hipLaunchKernelGGL((k_fgemm_f64<BM, BN, TA_, TB_, RED>), g1, dim3(256), 0, s, m, n, k, A, \
+                       lda, B, ldb, C, ldc, p, pinv, half, alpha, beta, ksteps, ntx, nty)
     if (!ta && !tb) FFP_LAUNCH(false, false);
     else if (ta && !tb) FFP_LAUNCH(true, false);
     else if (!ta && tb) FFP_LAUNCH(false, true);

@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kI8Threads) void k_fgemm_i8(const int8_t *__restric
                                                         int64_t Kp, int64_t planeA, int64_t planeB, int64_t m,
                                                         int64_t n, int32_t *__restrict__ C, int64_t ldc, double p,
                                                         double pinv, double alpha, double beta, double w1,
-                                                        double w2, double w3, double w4) {
+                                                        double w2, double w3, double w4, int ntx, int nty) {
     constexpr int NS = 2 * L - 1;        // shift classes
     constexpr int BM = kI8BM, BN = kI8BN, BK = kI8BK;
     constexpr int ROW = BK + 16;         // padded LDS row (bytes)
@@ -119,7 +119,9 @@ __global__ __launch_bounds__(kI8Threads) void k_fgemm_i8(const int8_t *__restric
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
-    const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+    int ty, tx;
+    xcd_tile(blockIdx.x, ntx, nty, ty, tx);
+    const int64_t m0 = (int64_t)ty * BM, n0 = (int64_t)tx * BN;
 
     // global -> register staging: L*(BM+BN)*BK/16 chunks of 16 bytes
     constexpr int CH_A = L * BM * BK / 16, CH_B = L * BN * BK / 16;
@@ -267,9 +269,10 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
             ProfScope prof(FFP_PATH_INT8, 2.0 * (double)m * (double)n * (double)kc, s,
                            4.0 * ((double)m * (double)kc + (double)kc * (double)n +
                                   (be != 0.0 ? 2.0 : 1.0) * (double)m * (double)n));
-            hipLaunchKernelGGL((k_fgemm_i8<L>), dim3((unsigned)(Np / kI8BN), (unsigned)(Mp / kI8BM)), dim3(kI8Threads),
-                               0, s, Ad, Bd, Kp, planeA, planeB, m, n, C, ldc, F.pd, F.pinv, (double)alpha, be,
-                               wts[0], wts[1], wts[2], wts[3]);
+            const int ntx = (int)(Np / kI8BN), nty = (int)(Mp / kI8BM);
+            hipLaunchKernelGGL((k_fgemm_i8<L>), dim3((unsigned)(ntx * nty)), dim3(kI8Threads), 0, s, Ad, Bd, Kp,
+                               planeA, planeB, m, n, C, ldc, F.pd, F.pinv, (double)alpha, be, wts[0], wts[1],
+                               wts[2], wts[3], ntx, nty);
         }
         FFP_HIP_CHECK(hipGetLastError());
         ws.release(mk);
