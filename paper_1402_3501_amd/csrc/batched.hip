@@ -19,7 +19,7 @@
 
 namespace ffp {
 
-constexpr int kBT = 256;                      // threads per workgroup
+constexpr int kBT = 1024;                     // threads per workgroup
 constexpr int kBMax = FFP_BATCH_MAX_DIM;      // max rows / columns
 constexpr int kBW = kBMax / 32;               // mask words
 constexpr int kBStack = 24;
@@ -43,92 +43,106 @@ enum { BT_FIN = 0, BT_ROW = 1, BT_COL = 2 };
 
 __device__ __forceinline__ bool bbit(const uint32_t *m, int i) { return (m[i >> 5] >> (i & 31)) & 1u; }
 
-__device__ static int bpopc(const uint32_t *m, int nw) {
-    int c = 0;
-    for (int w = 0; w < nw; ++w) c += __popc(m[w]);
-    return c;
+// Walk to the next one-row / one-column region (or finish), by one wave:
+// lane w holds word w of every row / column mask, so each mask operation of
+// a frame is a handful of wave-wide instructions (popcounts by shuffle
+// reduction, "first k set bits" by a prefix scan of the words' popcounts)
+// rather than a loop of dependent scalar LDS accesses (one thread doing the
+// same walk cost ~50 us per pivot).  Regions none of whose active rows has a
+// nonzero in the active columns hold no pivot and are skipped whole (S.nz);
+// this only prunes the walk, the regions that are visited and their order
+// are those of the recursion.  Called by all 64 lanes of wave 0.
+__device__ __forceinline__ int wsum(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
 }
-__device__ static int bfirst(const uint32_t *m, int nw) {
-    for (int w = 0; w < nw; ++w)
-        if (m[w]) return w * 32 + __ffs(m[w]) - 1;
-    return -1;
-}
-__device__ static void bfirst_k(const uint32_t *m, int nw, int k, uint32_t *out) {
-    for (int w = 0; w < nw; ++w) {
-        uint32_t x = m[w];
-        const int c = __popc(x);
-        if (k >= c) { out[w] = x; k -= c; }
-        else {
-            uint32_t o = 0;
-            while (k > 0) { const uint32_t low = x & (~x + 1u); o |= low; x ^= low; --k; }
-            out[w] = o;
-        }
+// the k lowest set bits of the wave-distributed mask x (k <= popcount)
+__device__ __forceinline__ uint32_t wfirst_k(uint32_t x, int k, int lane) {
+    const int c = __popc(x);
+    int incl = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off);
+        if (lane >= off) incl += o;
     }
+    const int excl = incl - c;
+    if (incl <= k) return x;
+    if (excl >= k) return 0u;
+    uint32_t o = 0;
+    for (int t = k - excl; t > 0; --t) {
+        const uint32_t low = x & (~x + 1u);
+        o |= low;
+        x ^= low;
+    }
+    return o;
+}
+// index of the lowest set bit of the wave-distributed mask x (x != 0)
+__device__ __forceinline__ int wfirst(uint32_t x) {
+    const uint64_t b = __ballot(x != 0u);
+    const int w = __ffsll((long long)b) - 1;
+    const uint32_t xw = (uint32_t)__shfl((int)x, w);
+    return w * 32 + __ffs(xw) - 1;
 }
 
-// one thread: walk to the next one-row / one-column region (or finish).
-// Regions none of whose active rows has a nonzero in the active columns hold
-// no pivot and are skipped whole (S.nz); this only prunes the walk, the
-// regions that are visited and their order are those of the recursion.
-__device__ static void bwalk(BShared &S, int nwr, int nwc) {
-    while (S.sp > 0) {
-        BFrame &f = S.st[S.sp - 1];
-        if (f.stage == 0) {
-            const int nr = bpopc(f.rows, nwr), nc = bpopc(f.cols, nwc);
-            if (nr == 0 || nc == 0) { S.sp--; continue; }
+__device__ __noinline__ static void bwalk_w(BShared &S, int nwr, int nwc, int lane) {
+    const bool lr = lane < nwr, lc = lane < nwc;
+    const uint32_t rd = lr ? S.rowdone[lane] : 0u, cd = lc ? S.coldone[lane] : 0u, nz = lr ? S.nz[lane] : 0u;
+    int sp = S.sp;
+    int type = BT_FIN, bx = 0;
+    while (sp > 0) {
+        BFrame &f = S.st[sp - 1];
+        const int stage = f.stage;
+        const uint32_t rows = lr ? f.rows[lane] : 0u, cols = lc ? f.cols[lane] : 0u;
+        if (stage == 0) {
+            const int nr = wsum(__popc(rows)), nc = wsum(__popc(cols));
+            if (nr == 0 || nc == 0) { --sp; continue; }
             // no active row of the region has a nonzero left: no pivot in it
-            bool live = false;
-            for (int w = 0; w < nwr; ++w) live |= (f.rows[w] & ~S.rowdone[w] & S.nz[w]) != 0u;
-            if (!live) { S.sp--; continue; }
+            if (__ballot((rows & ~rd & nz) != 0u) == 0ull) { --sp; continue; }
             if (nr == 1) {
-                S.type = BT_ROW;
-                S.bx = bfirst(f.rows, nwr);
-                for (int w = 0; w < nwc; ++w) S.mask[w] = f.cols[w];
-                S.sp--;
-                return;
+                type = BT_ROW;
+                bx = wfirst(rows);
+                if (lc) S.mask[lane] = cols;
+                --sp;
+                break;
             }
             if (nc == 1) {
-                S.type = BT_COL;
-                S.bx = bfirst(f.cols, nwc);
-                for (int w = 0; w < nwr; ++w) S.mask[w] = f.rows[w];
-                S.sp--;
-                return;
+                type = BT_COL;
+                bx = wfirst(cols);
+                if (lr) S.mask[lane] = rows;
+                --sp;
+                break;
             }
-            bfirst_k(f.rows, nwr, nr / 2, f.top);
-            bfirst_k(f.cols, nwc, nc / 2, f.left);
-            f.stage = 1;
-            BFrame &c = S.st[S.sp++];
-            for (int w = 0; w < nwr; ++w) c.rows[w] = f.top[w];
-            for (int w = 0; w < nwc; ++w) c.cols[w] = f.left[w];
-            c.stage = 0;
+            const uint32_t top = wfirst_k(rows, nr / 2, lane), left = wfirst_k(cols, nc / 2, lane);
+            BFrame &c = S.st[sp];
+            if (lr) { f.top[lane] = top; c.rows[lane] = top; }
+            if (lc) { f.left[lane] = left; c.cols[lane] = left; }
+            if (lane == 0) { f.stage = 1; c.stage = 0; }
+            ++sp;
             continue;
         }
+        const uint32_t top = lr ? f.top[lane] : 0u, left = lc ? f.left[lane] : 0u;
+        const uint32_t bot = rows & ~top, right = cols & ~left;
         bool pushed = false;
-        for (int st = f.stage; st <= 3 && !pushed; ++st) {
-            bool any_r = false, any_c = false;
-            uint32_t cr[kBW], cc[kBW];
-            for (int w = 0; w < nwr; ++w) {
-                const uint32_t top = f.top[w], bot = f.rows[w] & ~f.top[w];
-                cr[w] = st == 1 ? (top & ~S.rowdone[w]) : st == 2 ? bot : (bot & ~S.rowdone[w]);
-                any_r |= cr[w] != 0;
-            }
-            for (int w = 0; w < nwc; ++w) {
-                const uint32_t left = f.left[w], right = f.cols[w] & ~f.left[w];
-                cc[w] = st == 1 ? right : st == 2 ? (left & ~S.coldone[w]) : (right & ~S.coldone[w]);
-                any_c |= cc[w] != 0;
-            }
-            if (any_r && any_c) {
-                f.stage = st + 1;
-                BFrame &c = S.st[S.sp++];
-                for (int w = 0; w < nwr; ++w) c.rows[w] = cr[w];
-                for (int w = 0; w < nwc; ++w) c.cols[w] = cc[w];
-                c.stage = 0;
+        for (int st = stage; st <= 3 && !pushed; ++st) {
+            const uint32_t cr = st == 1 ? (top & ~rd) : st == 2 ? bot : (bot & ~rd);
+            const uint32_t cc = st == 1 ? right : st == 2 ? (left & ~cd) : (right & ~cd);
+            if (__ballot(cr != 0u) != 0ull && __ballot(cc != 0u) != 0ull) {
+                BFrame &c = S.st[sp];
+                if (lr) c.rows[lane] = cr;
+                if (lc) c.cols[lane] = cc;
+                if (lane == 0) { f.stage = st + 1; c.stage = 0; }
+                ++sp;
                 pushed = true;
             }
         }
-        if (!pushed) S.sp--;
+        if (!pushed) --sp;
     }
-    S.type = BT_FIN;
+    if (lane == 0) {
+        S.sp = sp;
+        S.type = type;
+        S.bx = bx;
+    }
 }
 
 __global__ void k_batch_reset(int *counter) { *counter = 0; }
@@ -184,9 +198,9 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
         }
         __syncthreads();
         while (true) {
-            if (tid == 0) {
-                bwalk(S, nwr, nwc);
-                S.piv = INT_MAX;
+            if (tid < 64) {
+                bwalk_w(S, nwr, nwc, tid);
+                if (tid == 0) S.piv = INT_MAX;
             }
             __syncthreads();
             const int type = S.type, bx = S.bx;
@@ -221,7 +235,8 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
             __syncthreads();
             // rank-one update of the active block: wave w takes rows w*RU ..,
             // RU rows at a time, lane c the columns c, c + 64, .., so that every
-            // lane has RU x CH independent loads in flight
+            // lane has RU x CH independent loads in flight (sixteen waves: 64
+            // rows per round of loads)
             {
                 constexpr int RU = 4, CH = 4;
                 const int wv = tid >> 6, ln = tid & 63, nch = (n + 63) >> 6;
@@ -345,7 +360,7 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
 }
 
 static int batched_grid(int32_t batch) {
-    int g = 512;  // two workgroups per compute unit of an MI355X
+    int g = 256;  // one 1024-thread workgroup per compute unit of an MI355X
     return batch < g ? batch : g;
 }
 
