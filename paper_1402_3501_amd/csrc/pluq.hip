@@ -422,15 +422,30 @@ static int iota(int32_t *v, int64_t n, hipStream_t s) {
 // ===================================================================== host recursion
 namespace {
 std::mutex g_pin_mu;
-int64_t *g_pin = nullptr;  // pinned host word for rank read-back
+int64_t *g_pin = nullptr;  // pinned host word for the flag read-back
+// Host words the leaves of the general recursion write their rank into
+// directly (pinned, coherent, device-visible): the host reads a rank after
+// one stream synchronisation, with no copy on the stream.  One word per
+// concurrent call, taken from a pool and kept for the life of the process.
+struct RankWord {
+    int64_t *host = nullptr, *dev = nullptr;
+};
+std::vector<RankWord> g_rank_pool;
 
-int read_rank(const int64_t *dev, int64_t *out, hipStream_t s) {
+int rank_word_get(RankWord *w) {
     std::lock_guard<std::mutex> g(g_pin_mu);
-    if (!g_pin) FFP_HIP_CHECK(hipHostMalloc((void **)&g_pin, 64, hipHostMallocDefault));
-    FFP_HIP_CHECK(hipMemcpyAsync(g_pin, dev, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    FFP_HIP_CHECK(hipStreamSynchronize(s));
-    *out = *g_pin;
+    if (!g_rank_pool.empty()) {
+        *w = g_rank_pool.back();
+        g_rank_pool.pop_back();
+        return FFP_OK;
+    }
+    FFP_HIP_CHECK(hipHostMalloc((void **)&w->host, 64, hipHostMallocMapped | hipHostMallocCoherent));
+    FFP_HIP_CHECK(hipHostGetDevicePointer((void **)&w->dev, w->host, 0));
     return FFP_OK;
+}
+void rank_word_put(const RankWord &w) {
+    std::lock_guard<std::mutex> g(g_pin_mu);
+    g_rank_pool.push_back(w);
 }
 
 // A second stream (one per device, default priority) for the triangular
@@ -475,8 +490,15 @@ struct Ctx {
     const Field *F;
     Arena *ws;
     hipStream_t s;
-    int64_t *rank_dev;  // one device word
+    int64_t *rank_dev;   // device address of a pinned host word the leaves write their rank to
+    int64_t *rank_host;  // the same word for the host
 };
+
+int read_rank(const Ctx &c, int64_t *out) {
+    FFP_HIP_CHECK(hipStreamSynchronize(c.s));
+    *out = *(const volatile int64_t *)c.rank_host;
+    return FFP_OK;
+}
 
 int fgemm_sub(Ctx &c, int64_t m, int64_t n, int64_t k, const int32_t *A, int64_t lda, const int32_t *B,
               int64_t ldb, int32_t *C, int64_t ldc) {
@@ -570,7 +592,7 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
     const Field &F = *c.F;
     if (leaf64_fits(m, n)) {
         FFP_CHECK(leaf64_launch(F, m, n, A, lda, P, Q, c.rank_dev, nullptr, nullptr, nullptr, s));
-        return read_rank(c.rank_dev, rank, s);
+        return read_rank(c, rank);
     }
     if (leaf_fits(m, n)) {
         const bool red = F.kexact < kLMaxDim;
@@ -581,7 +603,7 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
             hipLaunchKernelGGL((k_pluq_leaf<false>), dim3(1), dim3(kLT), 0, s, (int)m, (int)n, A, lda, P, Q,
                                c.rank_dev, F.pd, F.pinv, (int32_t)F.half, F.kexact);
         FFP_HIP_CHECK(hipGetLastError());
-        return read_rank(c.rank_dev, rank, s);
+        return read_rank(c, rank);
     }
     const int64_t m1 = m / 2, n1 = n / 2;
     // ---- 1. top-left tile
@@ -734,9 +756,15 @@ size_t pluq_ws(int64_t m, int64_t n, const Field &F, int path) {
 
 int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
              int64_t *r, Arena &ws, hipStream_t s) {
-    int64_t *rank_dev = (int64_t *)ws.take(256);
-    if (!rank_dev) return FFP_E_WORKSPACE;
-    Ctx c{path, &F, &ws, s, rank_dev};
+    int64_t *flag_dev = (int64_t *)ws.take(256);
+    if (!flag_dev) return FFP_E_WORKSPACE;
+    RankWord rw;
+    FFP_CHECK(rank_word_get(&rw));
+    struct WordBack {
+        RankWord w;
+        ~WordBack() { rank_word_put(w); }
+    } word_back{rw};
+    Ctx c{path, &F, &ws, s, rw.dev, rw.host};
     if (m > 64 && n > 64 && !getenv("FFP_PLUQ_GENERAL_ONLY")) {
         // speculate that A has generic rank profile (keep a copy to fall back)
         const size_t mk = ws.mark();
@@ -744,7 +772,7 @@ int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t
         const size_t nblk = (size_t)(((m < n ? m : n) + 63) / 64);
         double *Li = (double *)ws.take(nblk * kBlk * sizeof(double));
         double *Ui = (double *)ws.take(nblk * kBlk * sizeof(double));
-        int *gflag = (int *)rank_dev + 4;
+        int *gflag = (int *)flag_dev;
         if (!backup || !Li || !Ui) return FFP_E_WORKSPACE;
         FFP_CHECK(copy2d(m, n, A, lda, backup, n, s));
         hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, gflag, 0);
