@@ -177,6 +177,27 @@ int ffp_pluq_batched(int32_t batch, const int32_t *m_arr, const int32_t *n_arr, 
                      ffp_stream_t stream);
 
 /* --------------------------------------------------------------------------
+ * pluq_batched_tune -- autotuning of the batched launch: the same call as
+ * ffp_pluq_batched, run once with each of the library's FFP_BATCH_SHAPES
+ * launch shapes (workgroup size x workgroups per compute unit), each timed
+ * with HIP events on `stream`, the batch restored from a copy in the
+ * workspace before each run.  The fastest shape is kept for later
+ * ffp_pluq_batched calls with the same (device, batch, max_m, max_n); on
+ * return the batch is factored exactly as by ffp_pluq_batched.  Synchronises
+ * `stream` (call it before capturing the batched call in a graph).
+ *   a_elems: number of entries of A_packed (all matrices);
+ *   shape_out: host int receiving the chosen shape index (may be NULL);
+ *   ms_out: host float[FFP_BATCH_SHAPES] receiving each shape's time (may be NULL).
+ * -------------------------------------------------------------------------- */
+#define FFP_BATCH_SHAPES 2
+size_t ffp_pluq_batched_tune_workspace(int32_t batch, int32_t max_m, int32_t max_n, int64_t a_elems);
+int ffp_pluq_batched_tune(int32_t batch, const int32_t *m_arr, const int32_t *n_arr, int32_t max_m,
+                          int32_t max_n, uint32_t p, int32_t *A_packed, int64_t a_elems, const int64_t *A_off,
+                          int32_t *P_packed, const int64_t *P_off, int32_t *Q_packed, const int64_t *Q_off,
+                          int32_t *rank_arr, int32_t *rrp_packed, int32_t *crp_packed, int path, int *shape_out,
+                          float *ms_out, void *ws, size_t ws_bytes, ffp_stream_t stream);
+
+/* --------------------------------------------------------------------------
  * Host helpers (host pointers): conversion between an index vector and the
  * LAPACK laswp form (sequence of swaps: for i = 0..len-1, swap entries i and
  * ipiv[i]).  perm[i] = original index placed at position i.

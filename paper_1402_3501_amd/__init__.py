@@ -21,6 +21,7 @@ PATH_AUTO, PATH_FP64, PATH_INT8 = 0, 1, 2
 P_MAX_FP64 = 94906249
 P_MAX_INT8 = 16711421
 BATCH_MAX_DIM = 1024
+BATCH_SHAPES = 2  # launch shapes the batched autotuner chooses from
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libffpluq.so")
@@ -59,6 +60,9 @@ def load():
         "ffp_pluq": ([i64, i64, u32, vp, i64, vp, vp, vp, ctypes.POINTER(i64), vp, vp, i32, vp, sz, vp], i32),
         "ffp_pluq_batched_workspace": ([i32, i32, i32, u32, i32], sz),
         "ffp_pluq_batched": ([i32, vp, vp, i32, i32, u32, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, sz, vp], i32),
+        "ffp_pluq_batched_tune_workspace": ([i32, i32, i32, i64], sz),
+        "ffp_pluq_batched_tune": ([i32, vp, vp, i32, i32, u32, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, i32,
+                                   ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), vp, sz, vp], i32),
         "ffp_perm_to_swaps": ([i64, vp, vp], i32),
         "ffp_swaps_to_perm": ([i64, vp, vp], i32),
         "ffp_profile_enable": ([i32], i32),
@@ -275,6 +279,45 @@ def pluq_batched(ms, ns, A_packed, A_off, p: int, path: int = PATH_AUTO, max_m: 
                                 _vec(Q_off, "Q_off", torch.int64), _vec(rank, "rank"), _vec(rrp, "rrp"),
                                 _vec(crp, "crp"), path, ws, need, _stream(A_packed)), "ffp_pluq_batched")
     return BatchedResult(P, Q, rank[:batch], rrp, crp)
+
+
+def pluq_batched_tune(ms, ns, A_packed, A_off, p: int, path: int = PATH_AUTO):
+    """Time each batched launch shape on this batch (restoring it in between),
+    keep the fastest for later calls on batches of the same description, and
+    leave the batch factored.  Returns (BatchedResult, chosen shape, list of
+    per-shape milliseconds).  Synchronises."""
+    torch = _torch()
+    lib = load()
+    dev = A_packed.device
+    batch = int(ms.numel())
+    ms_h = ms.cpu().to(torch.int64)
+    ns_h = ns.cpu().to(torch.int64)
+    max_m = int(ms_h.max()) if batch else 0
+    max_n = int(ns_h.max()) if batch else 0
+    P_off = torch.zeros(batch, dtype=torch.int64)
+    Q_off = torch.zeros(batch, dtype=torch.int64)
+    if batch > 1:
+        P_off[1:] = torch.cumsum(ms_h, 0)[:-1]
+        Q_off[1:] = torch.cumsum(ns_h, 0)[:-1]
+    tm, tn = int(ms_h.sum()), int(ns_h.sum())
+    P_off, Q_off = P_off.to(dev), Q_off.to(dev)
+    P = torch.empty(max(tm, 1), dtype=torch.int32, device=dev)
+    Q = torch.empty(max(tn, 1), dtype=torch.int32, device=dev)
+    rrp = torch.empty(max(tm, 1), dtype=torch.int32, device=dev)
+    crp = torch.empty(max(tn, 1), dtype=torch.int32, device=dev)
+    rank = torch.empty(max(batch, 1), dtype=torch.int32, device=dev)
+    a_elems = int(A_packed.numel())
+    need = lib.ffp_pluq_batched_tune_workspace(batch, max_m, max_n, a_elems)
+    keep, ws = _workspace(need, dev)
+    shape = ctypes.c_int(-1)
+    times = (ctypes.c_float * 8)()
+    _check(lib.ffp_pluq_batched_tune(batch, _vec(ms, "ms"), _vec(ns, "ns"), max_m, max_n, p,
+                                     _vec(A_packed, "A_packed"), a_elems, _vec(A_off, "A_off", torch.int64),
+                                     _vec(P, "P"), _vec(P_off, "P_off", torch.int64), _vec(Q, "Q"),
+                                     _vec(Q_off, "Q_off", torch.int64), _vec(rank, "rank"), _vec(rrp, "rrp"),
+                                     _vec(crp, "crp"), path, ctypes.byref(shape), times, ws, need,
+                                     _stream(A_packed)), "ffp_pluq_batched_tune")
+    return BatchedResult(P, Q, rank[:batch], rrp, crp), shape.value, [times[i] for i in range(BATCH_SHAPES)]
 
 
 def pluq_batched_into(ms, ns, max_m: int, max_n: int, A_packed, A_off, P, P_off, Q, Q_off, rank, rrp, crp,

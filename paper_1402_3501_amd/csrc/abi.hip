@@ -287,6 +287,42 @@ int ffp_pluq_batched(int32_t batch, const int32_t *m_arr, const int32_t *n_arr, 
                             Q_off, rank_arr, rrp_packed, crp_packed, ar, (hipStream_t)stream);
 }
 
+size_t ffp_pluq_batched_tune_workspace(int32_t batch, int32_t max_m, int32_t max_n, int64_t a_elems) {
+    if (batch <= 0) return 0;
+    return pluq_batched_ws(batch, max_m, max_n) + (size_t)(a_elems > 0 ? a_elems : 0) * 4 + 512;
+}
+
+int ffp_pluq_batched_tune(int32_t batch, const int32_t *m_arr, const int32_t *n_arr, int32_t max_m, int32_t max_n,
+                          uint32_t p, int32_t *A_packed, int64_t a_elems, const int64_t *A_off, int32_t *P_packed,
+                          const int64_t *P_off, int32_t *Q_packed, const int64_t *Q_off, int32_t *rank_arr,
+                          int32_t *rrp_packed, int32_t *crp_packed, int path, int *shape_out, float *ms_out,
+                          void *ws, size_t ws_bytes, ffp_stream_t stream) {
+    if (batch < 0) return -1;
+    if (batch == 0) return FFP_OK;
+    if (!m_arr) return -2;
+    if (!n_arr) return -3;
+    if (max_m < 0 || max_m > FFP_BATCH_MAX_DIM) return -4;
+    if (max_n < 0 || max_n > FFP_BATCH_MAX_DIM) return -5;
+    FFP_CHECK(check_field(p, path, 6, 17));
+    if (!A_packed) return -7;
+    if (a_elems < 0) return -8;
+    if (!A_off) return -9;
+    if (!P_packed) return -10;
+    if (!P_off) return -11;
+    if (!Q_packed) return -12;
+    if (!Q_off) return -13;
+    if (!rank_arr) return -14;
+    const size_t need = ffp_pluq_batched_tune_workspace(batch, max_m, max_n, a_elems);
+    if (!ws || ws_bytes < need) return FFP_E_WORKSPACE;
+    Field F(p);
+    Arena ar;
+    ar.base = (char *)ws;
+    ar.cap = ws_bytes;
+    return pluq_batched_tune(F, batch, m_arr, n_arr, max_m, max_n, A_packed, a_elems, A_off, P_packed, P_off,
+                             Q_packed, Q_off, rank_arr, rrp_packed, crp_packed, ar, (hipStream_t)stream, shape_out,
+                             ms_out);
+}
+
 // ------------------------------------------------------------------ host helpers
 int ffp_perm_to_swaps(int64_t len, const int32_t *perm, int32_t *ipiv) {
     if (len < 0) return -1;

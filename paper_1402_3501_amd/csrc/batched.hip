@@ -12,14 +12,17 @@
 // returns for the matrix alone.  The factors are then written back with the
 // final row and column order, together with P, Q, the rank and the sorted
 // rank profiles.
+#include <algorithm>
 #include <climits>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "ffp_internal.hpp"
 #include "ffp_device.hpp"
 
 namespace ffp {
 
-constexpr int kBT = 1024;                     // threads per workgroup
 constexpr int kBMax = FFP_BATCH_MAX_DIM;      // max rows / columns
 constexpr int kBW = kBMax / 32;               // mask words
 constexpr int kBStack = 24;
@@ -147,6 +150,7 @@ __device__ __noinline__ static void bwalk_w(BShared &S, int nwr, int nwc, int la
 
 __global__ void k_batch_reset(int *counter) { *counter = 0; }
 
+template <int kBT>
 __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32_t *__restrict__ m_arr,
                                                       const int32_t *__restrict__ n_arr, int32_t *__restrict__ A,
                                                       const int64_t *__restrict__ A_off, int32_t *__restrict__ P,
@@ -359,30 +363,126 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
     }
 }
 
-static int batched_grid(int32_t batch) {
-    int g = 256;  // one 1024-thread workgroup per compute unit of an MI355X
+// Launch shapes (threads per workgroup, workgroups per compute unit): one
+// 1024-thread workgroup per CU (sixteen waves on each matrix, the default),
+// or two 256-thread workgroups per CU (twice the matrices in flight, a
+// quarter of the waves on each).  ffp_pluq_batched_tune times them on the
+// caller's batch and keeps the faster one for batches of that description.
+struct BShape {
+    int threads, per_cu;
+};
+constexpr BShape kShapes[] = {{1024, 1}, {256, 2}};
+constexpr int kNShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tuned;  // (device, batch, max_m, max_n) -> shape
+
+static int device_cus() {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return cus > 0 ? cus : 256;
+}
+static int batched_grid(int32_t batch, int shape) {
+    const int g = device_cus() * kShapes[shape].per_cu;
     return batch < g ? batch : g;
+}
+static int max_grid(int32_t batch) {
+    int g = 0;
+    for (int i = 0; i < kNShapes; ++i) g = std::max(g, batched_grid(batch, i));
+    return g;
 }
 
 size_t pluq_batched_ws(int32_t batch, int32_t max_m, int32_t max_n) {
     const size_t slot = (size_t)(max_m > 0 ? max_m : 1) * (size_t)(max_n > 0 ? max_n : 1);
-    return 256 + (size_t)batched_grid(batch) * slot * 4 + 256;
+    return 256 + (size_t)max_grid(batch) * slot * 4 + 256;
+}
+
+static int tuned_shape(int32_t batch, int32_t max_m, int32_t max_n) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tuned.find(std::make_tuple(dev, batch, max_m, max_n));
+    return it == g_tuned.end() ? 0 : it->second;
+}
+
+static int launch_shape(int shape, const Field &F, int32_t batch, const int32_t *m_arr, const int32_t *n_arr,
+                        int32_t max_m, int32_t max_n, int32_t *A, const int64_t *A_off, int32_t *P,
+                        const int64_t *P_off, int32_t *Q, const int64_t *Q_off, int32_t *rank, int32_t *rrp,
+                        int32_t *crp, Arena &ws, hipStream_t s) {
+    const size_t mk = ws.mark();
+    int *counter = (int *)ws.take(256);
+    const int grid = batched_grid(batch, shape);
+    const int64_t slot = (int64_t)(max_m > 0 ? max_m : 1) * (int64_t)(max_n > 0 ? max_n : 1);
+    int32_t *slots = (int32_t *)ws.take((size_t)grid * (size_t)slot * 4);
+    if (!counter || !slots) return FFP_E_WORKSPACE;
+    // counter cleared by a kernel (not a memset) so that the sequence can be captured in a graph
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, counter);
+#define FFP_BAT(T_)                                                                                          \
+    hipLaunchKernelGGL((k_pluq_batched<T_>), dim3(grid), dim3(T_), 0, s, batch, m_arr, n_arr, A, A_off, P, P_off, \
+                       Q, Q_off, rank, rrp, crp, counter, slots, slot, F.pd, F.pinv, (int32_t)F.half)
+    if (kShapes[shape].threads == 1024) FFP_BAT(1024);
+    else FFP_BAT(256);
+#undef FFP_BAT
+    FFP_HIP_CHECK(hipGetLastError());
+    ws.release(mk);
+    return FFP_OK;
 }
 
 int pluq_batched_run(const Field &F, int32_t batch, const int32_t *m_arr, const int32_t *n_arr, int32_t max_m,
                      int32_t max_n, int32_t *A, const int64_t *A_off, int32_t *P, const int64_t *P_off, int32_t *Q,
                      const int64_t *Q_off, int32_t *rank, int32_t *rrp, int32_t *crp, Arena &ws, hipStream_t s) {
     if (batch <= 0) return FFP_OK;
-    int *counter = (int *)ws.take(256);
-    const int grid = batched_grid(batch);
-    const int64_t slot = (int64_t)(max_m > 0 ? max_m : 1) * (int64_t)(max_n > 0 ? max_n : 1);
-    int32_t *slots = (int32_t *)ws.take((size_t)grid * (size_t)slot * 4);
-    if (!counter || !slots) return FFP_E_WORKSPACE;
-    // counter cleared by a kernel (not a memset) so that the sequence can be captured in a graph
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, counter);
-    hipLaunchKernelGGL(k_pluq_batched, dim3(grid), dim3(kBT), 0, s, batch, m_arr, n_arr, A, A_off, P, P_off, Q,
-                       Q_off, rank, rrp, crp, counter, slots, slot, F.pd, F.pinv, (int32_t)F.half);
-    FFP_HIP_CHECK(hipGetLastError());
+    return launch_shape(tuned_shape(batch, max_m, max_n), F, batch, m_arr, n_arr, max_m, max_n, A, A_off, P, P_off,
+                        Q, Q_off, rank, rrp, crp, ws, s);
+}
+
+int pluq_batched_tune(const Field &F, int32_t batch, const int32_t *m_arr, const int32_t *n_arr, int32_t max_m,
+                      int32_t max_n, int32_t *A, int64_t a_elems, const int64_t *A_off, int32_t *P,
+                      const int64_t *P_off, int32_t *Q, const int64_t *Q_off, int32_t *rank, int32_t *rrp,
+                      int32_t *crp, Arena &ws, hipStream_t s, int *chosen, float *ms_out) {
+    if (batch <= 0) return FFP_OK;
+    // the pristine batch, restored before each timed run
+    int32_t *keep = (int32_t *)ws.take((size_t)a_elems * 4);
+    if (!keep) return FFP_E_WORKSPACE;
+    FFP_HIP_CHECK(hipMemcpyAsync(keep, A, (size_t)a_elems * 4, hipMemcpyDeviceToDevice, s));
+    hipEvent_t e0, e1;
+    FFP_HIP_CHECK(hipEventCreate(&e0));
+    FFP_HIP_CHECK(hipEventCreate(&e1));
+    int best = 0;
+    float best_ms = 0.f;
+    int rc = FFP_OK;
+    for (int sh = 0; sh < kNShapes && rc == FFP_OK; ++sh) {
+        if ((rc = (int)hipMemcpyAsync(A, keep, (size_t)a_elems * 4, hipMemcpyDeviceToDevice, s)) != 0) {
+            rc = FFP_E_HIP;
+            break;
+        }
+        (void)hipEventRecord(e0, s);
+        rc = launch_shape(sh, F, batch, m_arr, n_arr, max_m, max_n, A, A_off, P, P_off, Q, Q_off, rank, rrp, crp, ws, s);
+        (void)hipEventRecord(e1, s);
+        if (rc != FFP_OK) break;
+        if (hipEventSynchronize(e1) != hipSuccess) { rc = FFP_E_HIP; break; }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms_out) ms_out[sh] = ms;
+        if (sh == 0 || ms < best_ms) { best = sh; best_ms = ms; }
+    }
+    // leave the batch factored by the chosen shape
+    if (rc == FFP_OK && best != kNShapes - 1) {
+        if (hipMemcpyAsync(A, keep, (size_t)a_elems * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) rc = FFP_E_HIP;
+        else rc = launch_shape(best, F, batch, m_arr, n_arr, max_m, max_n, A, A_off, P, P_off, Q, Q_off, rank, rrp,
+                               crp, ws, s);
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != FFP_OK) return rc;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tuned[std::make_tuple(dev, batch, max_m, max_n)] = best;
+    }
+    if (chosen) *chosen = best;
     return FFP_OK;
 }
 

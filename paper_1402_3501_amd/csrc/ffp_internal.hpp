@@ -159,5 +159,9 @@ int pluq_batched_run(const Field &F, int32_t batch, const int32_t *m_arr, const 
                      int32_t max_m, int32_t max_n, int32_t *A, const int64_t *A_off, int32_t *P,
                      const int64_t *P_off, int32_t *Q, const int64_t *Q_off, int32_t *rank,
                      int32_t *rrp, int32_t *crp, Arena &ws, hipStream_t s);
+int pluq_batched_tune(const Field &F, int32_t batch, const int32_t *m_arr, const int32_t *n_arr, int32_t max_m,
+                      int32_t max_n, int32_t *A, int64_t a_elems, const int64_t *A_off, int32_t *P,
+                      const int64_t *P_off, int32_t *Q, const int64_t *Q_off, int32_t *rank, int32_t *rrp,
+                      int32_t *crp, Arena &ws, hipStream_t s, int *chosen, float *ms_out);
 
 }  // namespace ffp

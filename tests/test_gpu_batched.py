@@ -165,3 +165,37 @@ def test_batched_graph_capture_replays(lib, orc):
     out = (Aw.cpu().numpy(), P.cpu().numpy(), Q.cpu().numpy(), rank.cpu().numpy(), rrp.cpu().numpy(),
            crp.cpu().numpy())
     _compare(orc, ms, ns, A, off, p, out, range(0, batch, 12))
+
+
+def test_batched_autotune(lib, orc):
+    """The autotuner times every launch shape on the batch, leaves the batch
+    factored (equal to the plain batched call bit for bit), and later calls
+    on the same batch description give the same bits again."""
+    import torch
+    p = 131071
+    ms, ns, rs, A, off = wl.batch(300, 8, 300, p, 91)
+    dev = "cuda"
+    msd = torch.from_numpy(ms.astype(np.int32)).to(dev)
+    nsd = torch.from_numpy(ns.astype(np.int32)).to(dev)
+    offd = torch.from_numpy(off.astype(np.int64)).to(dev)
+    A0 = torch.from_numpy(A.astype(np.int32)).to(dev)
+    note("batched autotune: plain call")
+    Ae = A0.clone()
+    ref = lib.pluq_batched(msd, nsd, Ae, offd, p)
+    note("batched autotune: tune")
+    At = A0.clone()
+    res, shape, times = lib.pluq_batched_tune(msd, nsd, At, offd, p)
+    torch.cuda.synchronize()
+    assert 0 <= shape < lib.BATCH_SHAPES and len(times) == lib.BATCH_SHAPES and all(t > 0 for t in times)
+    assert times[shape] == min(times)
+    assert torch.equal(At, Ae)
+    assert torch.equal(res.P, ref.P) and torch.equal(res.Q, ref.Q) and torch.equal(res.rank, ref.rank)
+    note("batched autotune: call with the tuned shape")
+    A2 = A0.clone()
+    res2 = lib.pluq_batched(msd, nsd, A2, offd, p)
+    torch.cuda.synchronize()
+    assert torch.equal(A2, Ae) and torch.equal(res2.rank, ref.rank)
+    assert np.array_equal(res2.rank.cpu().numpy(), rs)
+    out = (A2.cpu().numpy(), res2.P.cpu().numpy(), res2.Q.cpu().numpy(), res2.rank.cpu().numpy(),
+           res2.rrp.cpu().numpy(), res2.crp.cpu().numpy())
+    _compare(orc, ms, ns, A, off, p, out, range(0, len(ms), 25))
