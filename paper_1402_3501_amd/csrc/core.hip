@@ -244,9 +244,32 @@ int copy2d(int64_t m, int64_t n, const int32_t *src, int64_t lds, int32_t *dst, 
     return FFP_OK;
 }
 
+// Small blocks in place through LDS, one workgroup: every source entry is
+// read before any is written, so one launch replaces the gather and the copy
+// back (the recursion permutes many small blocks).
+constexpr int64_t kPermLds = 16384;  // entries (64 KiB of LDS)
+
+__global__ __launch_bounds__(1024) void k_permute_lds(int64_t m, int64_t n, int32_t *__restrict__ A, int64_t lda,
+                                                      PermSpec rp, PermSpec cp) {
+    extern __shared__ int32_t pbuf[];
+    const int64_t tot = m * n;
+    for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int64_t i = e / n, j = e % n;
+        pbuf[e] = A[perm_apply(rp, i) * lda + perm_apply(cp, j)];
+    }
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) A[(e / n) * lda + e % n] = pbuf[e];
+}
+
 int permute_inplace(int64_t m, int64_t n, int32_t *A, int64_t lda, const PermSpec &rp,
                     const PermSpec &cp, Arena &ws, hipStream_t s) {
     if (m <= 0 || n <= 0 || (rp.identity() && cp.identity())) return FFP_OK;
+    if (m * n <= kPermLds) {
+        if (ws.counting) return FFP_OK;
+        hipLaunchKernelGGL(k_permute_lds, dim3(1), dim3(1024), (size_t)(m * n) * 4, s, m, n, A, lda, rp, cp);
+        FFP_HIP_CHECK(hipGetLastError());
+        return FFP_OK;
+    }
     const size_t mk = ws.mark();
     int32_t *tmp = (int32_t *)ws.take((size_t)m * (size_t)n * 4);
     if (ws.counting) { ws.release(mk); return FFP_OK; }

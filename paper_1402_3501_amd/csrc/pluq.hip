@@ -363,12 +363,9 @@ struct NodeDims {
     int64_t m, n, m1, n1, r1, r2, r3, r4;
 };
 
-__global__ void k_node_index(NodeDims d, const int32_t *__restrict__ Pcur, const int32_t *__restrict__ P2,
-                             const int32_t *__restrict__ P3, const int32_t *__restrict__ P4,
-                             const int32_t *__restrict__ Qcur, const int32_t *__restrict__ Q2,
-                             const int32_t *__restrict__ Q3, const int32_t *__restrict__ Q4,
-                             int32_t *__restrict__ Pnew, int32_t *__restrict__ Qnew) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__device__ __forceinline__ int32_t node_index(const NodeDims &d, int64_t t, const int32_t *Pcur, const int32_t *P2,
+                                              const int32_t *P3, const int32_t *P4, const int32_t *Qcur,
+                                              const int32_t *Q2, const int32_t *Q3, const int32_t *Q4) {
     if (t < d.m) {
         // destination order [a f g R f' rest] -> source position in the current layout
         const int64_t i = t;
@@ -385,8 +382,8 @@ __global__ void k_node_index(NodeDims d, const int32_t *__restrict__ Pcur, const
         else if (s < d.m1) v = Pcur[d.r1 + P2[s - d.r1]];
         else if (s < d.m1 + d.r3) v = d.m1 + P3[s - d.m1];
         else v = d.m1 + P3[d.r3 + P4[s - d.m1 - d.r3]];
-        Pnew[i] = (int32_t)v;
-    } else if (t < d.m + d.n) {
+        return (int32_t)v;
+    } else {
         const int64_t j = t - d.m;
         const int64_t a = d.r1, f = d.r2, g = d.r3, R = d.r4, gp = d.n1 - d.r1 - d.r3;
         int64_t s;
@@ -401,7 +398,36 @@ __global__ void k_node_index(NodeDims d, const int32_t *__restrict__ Pcur, const
         else if (s < d.n1) v = Qcur[d.r1 + Q3[s - d.r1]];
         else if (s < d.n1 + d.r2) v = d.n1 + Q2[s - d.n1];
         else v = d.n1 + Q2[d.r2 + Q4[s - d.n1 - d.r2]];
-        Qnew[j] = (int32_t)v;
+        return (int32_t)v;
+    }
+}
+__global__ void k_node_index(NodeDims d, const int32_t *__restrict__ Pcur, const int32_t *__restrict__ P2,
+                             const int32_t *__restrict__ P3, const int32_t *__restrict__ P4,
+                             const int32_t *__restrict__ Qcur, const int32_t *__restrict__ Q2,
+                             const int32_t *__restrict__ Q3, const int32_t *__restrict__ Q4,
+                             int32_t *__restrict__ Pnew, int32_t *__restrict__ Qnew) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < d.m + d.n) {
+        const int32_t v = node_index(d, t, Pcur, P2, P3, P4, Qcur, Q2, Q3, Q4);
+        if (t < d.m) Pnew[t] = v;
+        else Qnew[t - d.m] = v;
+    }
+}
+// the same for a small node in place, one workgroup, through LDS
+__global__ __launch_bounds__(1024) void k_node_index_lds(NodeDims d, int32_t *__restrict__ P,
+                                                         const int32_t *__restrict__ P2,
+                                                         const int32_t *__restrict__ P3,
+                                                         const int32_t *__restrict__ P4, int32_t *__restrict__ Q,
+                                                         const int32_t *__restrict__ Q2,
+                                                         const int32_t *__restrict__ Q3,
+                                                         const int32_t *__restrict__ Q4) {
+    extern __shared__ int32_t ibuf[];
+    const int64_t tot = d.m + d.n;
+    for (int64_t t = threadIdx.x; t < tot; t += blockDim.x) ibuf[t] = node_index(d, t, P, P2, P3, P4, Q, Q2, Q3, Q4);
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < tot; t += blockDim.x) {
+        if (t < d.m) P[t] = ibuf[t];
+        else Q[t - d.m] = ibuf[t];
     }
 }
 
@@ -669,15 +695,21 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
     }
     // ---- 9. local permutations of this node
     {
-        int32_t *Pn = (int32_t *)ws.take((size_t)(m + n) * 4);
-        if (!Pn) return FFP_E_WORKSPACE;
         NodeDims d{m, n, m1, n1, r1, r2, r3, r4};
         const int64_t tot = m + n;
-        hipLaunchKernelGGL(k_node_index, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, d, P, P2, P3, P4,
-                           Q, Q2, Q3, Q4, Pn, Pn + m);
-        FFP_HIP_CHECK(hipGetLastError());
-        FFP_HIP_CHECK(hipMemcpyAsync(P, Pn, (size_t)m * 4, hipMemcpyDeviceToDevice, s));
-        FFP_HIP_CHECK(hipMemcpyAsync(Q, Pn + m, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+        if (tot <= 16384) {
+            hipLaunchKernelGGL(k_node_index_lds, dim3(1), dim3(1024), (size_t)tot * 4, s, d, P, P2, P3, P4, Q, Q2,
+                               Q3, Q4);
+            FFP_HIP_CHECK(hipGetLastError());
+        } else {
+            int32_t *Pn = (int32_t *)ws.take((size_t)(m + n) * 4);
+            if (!Pn) return FFP_E_WORKSPACE;
+            hipLaunchKernelGGL(k_node_index, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, d, P, P2, P3,
+                               P4, Q, Q2, Q3, Q4, Pn, Pn + m);
+            FFP_HIP_CHECK(hipGetLastError());
+            FFP_HIP_CHECK(hipMemcpyAsync(P, Pn, (size_t)m * 4, hipMemcpyDeviceToDevice, s));
+            FFP_HIP_CHECK(hipMemcpyAsync(Q, Pn + m, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+        }
     }
     ws.release(mk);
     *rank = r1 + r2 + r3 + r4;
