@@ -215,7 +215,7 @@ __device__ __forceinline__ void trsm_blk_body(int bid, int d, int64_t nv, const 
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * 256;
-            const int c = LEFT ? idx >> 4 : idx & 255, w = LEFT ? idx & 15 : idx >> 8;
+            const int c = LEFT ? idx / kVB : idx % kTBB, w = LEFT ? idx % kVB : idx / kTBB;
             const int cc = c < d ? c : d - 1;
             const int64_t vv = v0 + w < nv ? v0 + w : nv - 1;
             v[e] = LEFT ? B[(int64_t)cc * ldb + vv] : B[vv * ldb + cc];
@@ -223,7 +223,7 @@ __device__ __forceinline__ void trsm_blk_body(int bid, int d, int64_t nv, const 
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * 256;
-            const int c = LEFT ? idx >> 4 : idx & 255, w = LEFT ? idx & 15 : idx >> 8;
+            const int c = LEFT ? idx / kVB : idx % kTBB, w = LEFT ? idx % kVB : idx / kTBB;
             const int32_t x = (c < d && v0 + w < nv) ? v[e] : 0;
             S[c][w] = x > half ? x - ip : x;
         }
@@ -381,7 +381,7 @@ __device__ __forceinline__ void trsm_blk_body(int bid, int d, int64_t nv, const 
     }
     // ---- slab out
     for (int idx = tid; idx < kTBB * kVB; idx += 256) {
-        const int c = LEFT ? idx >> 4 : idx & 255, w = LEFT ? idx & 15 : idx >> 8;
+        const int c = LEFT ? idx / kVB : idx % kTBB, w = LEFT ? idx % kVB : idx / kTBB;
         if (c < d && v0 + w < nv) {
             const int32_t x = S[c][w];
             const int32_t y = x < 0 ? x + ip : x;
