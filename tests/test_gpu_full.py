@@ -67,3 +67,35 @@ def test_fgemm_8192_sampled_rows(lib, orc):
     rows = np.random.default_rng(1).choice(n, 12, replace=False)
     want = orc.fgemm(X[rows], Y, np.zeros((len(rows), n), np.int32), p, 1, 0)
     assert np.array_equal(got[rows], want)
+
+
+@pytest.mark.parametrize("side,uplo", [(0, 0), (1, 1)])
+def test_ftrsm_8192_sampled(lib, orc, side, uplo):
+    """The solves of the 8192 factorisation at full size, both paths (AUTO and
+    FP64, bit-identical): a left lower and a right upper 8192-triangle with
+    2048 right-hand sides; sampled columns (left) or rows (right) of the
+    solution recomputed by the oracle from the same triangle and the same
+    sampled right-hand sides (each depends on nothing else)."""
+    import torch
+    from paper_1402_3501_amd import PATH_AUTO, PATH_FP64
+    p = 131071
+    d, nv = 8192, 2048
+    T = wl.uniform(d, d, p, 301)
+    T[np.arange(d), np.arange(d)] = np.maximum(T[np.arange(d), np.arange(d)], 1)
+    B = wl.uniform(d, nv, p, 302) if side == 0 else wl.uniform(nv, d, p, 302)
+    Td = torch.from_numpy(T).cuda()
+    outs = []
+    for path in (PATH_AUTO, PATH_FP64):
+        note(f"ftrsm {d} side={side} uplo={uplo} path={path}")
+        Bd = torch.from_numpy(B).cuda()
+        lib.ftrsm(side, uplo, 0, 1, Td, Bd, p, 1, path=path)
+        torch.cuda.synchronize()
+        outs.append(Bd.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+    idx = np.random.default_rng(side).choice(nv, 3, replace=False)
+    if side == 0:
+        want = orc.ftrsm(side, uplo, 0, 1, T, np.ascontiguousarray(B[:, idx]), p, 1)
+        assert np.array_equal(outs[0][:, idx], want)
+    else:
+        want = orc.ftrsm(side, uplo, 0, 1, T, np.ascontiguousarray(B[idx, :]), p, 1)
+        assert np.array_equal(outs[0][idx, :], want)
