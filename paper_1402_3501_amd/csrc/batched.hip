@@ -264,12 +264,15 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
                             ok[cc] = c < n && c != y && !bbit(S.coldone, c);
                             u[cc] = ok[cc] ? S.urow[c] : 0.0;
                         }
+                        // unconditional loads at clamped addresses (a guarded load
+                        // waits before the next is issued); unused values are ignored
 #pragma unroll
                         for (int r = 0; r < RU; ++r)
 #pragma unroll
                             for (int cc = 0; cc < CH; ++cc) {
-                                const int c = ln + 64 * (ch0 + cc);
-                                v[r][cc] = (l[r] != 0.0 && ok[cc]) ? W[(int64_t)(i0 + r) * n + c] : 0;
+                                const int ir = i0 + r < m ? i0 + r : m - 1;
+                                const int c = ln + 64 * (ch0 + cc) < n ? ln + 64 * (ch0 + cc) : n - 1;
+                                v[r][cc] = W[(int64_t)ir * n + c];
                             }
 #pragma unroll
                         for (int r = 0; r < RU; ++r)
