@@ -324,8 +324,9 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
 // Entries are brought back to |W| <= (p-1)/2 + 3 every step (rounded
 // quotient), so q W - a u stays below 2^53 for every p the FP64 embedding
 // takes, and a pivot is zero mod p exactly when it is 0.0.  SMALLP selects
-// the inverse routine.  A zero pivot sets *gflag and leaves A untouched (A is
-// written only at the end); nothing runs once *gflag is set.
+// the inverse routine.  A zero pivot sets *gflag to 1 + its index on the
+// whole diagonal (diag0 = the block's offset there) and leaves A untouched
+// (A is written only at the end); nothing runs once *gflag is set.
 // With Linv / Uinv non-null the leaf also stores L^-1 and U^-1 of its k x k
 // diagonal block (k = min(mb, nb); 64 x 64 centred doubles, zero outside),
 // the base-case inverses of later triangular solves with these blocks.
@@ -342,7 +343,7 @@ __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *_
                                                       double *__restrict__ Linv, double *__restrict__ Uinv,
                                                       int inv_red, int kchunk, const int32_t *__restrict__ He,
                                                       const int32_t *__restrict__ Hd, int32_t *__restrict__ Pd,
-                                                      int pdn, int32_t *__restrict__ Pe, int pem) {
+                                                      int pdn, int32_t *__restrict__ Pe, int pem, int diag0) {
     static_assert(NW == 8, "four pivot rows per block share one row slot; two 256-thread inversion groups");
     constexpr int RPW = 64 / NW;  // rows per wave
     constexpr int KB = 4;         // elimination steps per barrier
@@ -434,18 +435,20 @@ __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *_
         double u[KB], um[KB], q[KB];
 #pragma unroll
         for (int j = 0; j < KB; ++j) u[j] = j < nbk ? sh.rowbuf[buf][j][lane] : 0.0;
-        bool zero = false;
+        int zj = -1;  // first zero pivot of the block
 #pragma unroll
         for (int j = 0; j < KB; ++j) {
 #pragma unroll
             for (int jj = 0; jj < j; ++jj) u[j] = step(u[j], um[jj], q[jj], kb + jj);
             q[j] = rld(u[j], kb + j);
             um[j] = lane > kb + j ? u[j] : 0.0;
-            if (j < nbk && q[j] == 0.0) zero = true;
+            if (j < nbk && q[j] == 0.0 && zj < 0) zj = j;
         }
-        if (zero) {
-            // every wave sees the same pivots and leaves here
-            if (tid == 0) *gflag = 1;
+        if (zj >= 0) {
+            // every wave sees the same pivots and leaves here; the flag
+            // records 1 + the pivot's index on the diagonal of the whole
+            // factorisation (every leading minor below that order is nonzero)
+            if (tid == 0) *gflag = 1 + diag0 + kb + zj;
             return;
         }
         if (tid < nbk) {
@@ -598,7 +601,7 @@ constexpr int kGenWaves = 8;
 
 int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
                   int64_t *rank_dev, int *gflag, double *Linv, double *Uinv, hipStream_t s, const int32_t *He,
-                  const int32_t *Hd, int32_t *Pd, int64_t pdn, int32_t *Pe, int64_t pem) {
+                  const int32_t *Hd, int32_t *Pd, int64_t pdn, int32_t *Pe, int64_t pem, int64_t diag0) {
     const bool red = F.kexact < 64;
     const bool small = F.p < (1u << 24);
 #define FFP_L64(R_, S_)                                                                                    \
@@ -620,10 +623,10 @@ int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda,
             return FFP_E_INTERNAL;
         if (small) hipLaunchKernelGGL((k_leaf_gen<true, kGenWaves>), dim3(1), dim3(64 * kGenWaves), 0, s, (int)m, (int)n, A,
                                       lda, F.pd, F.pinv, (int32_t)F.half, gflag, Linv, Uinv, inv_red, kchunk, He, Hd,
-                                      Pd, (int)pdn, Pe, (int)pem);
+                                      Pd, (int)pdn, Pe, (int)pem, (int)diag0);
         else hipLaunchKernelGGL((k_leaf_gen<false, kGenWaves>), dim3(1), dim3(64 * kGenWaves), 0, s, (int)m, (int)n, A,
                                 lda, F.pd, F.pinv, (int32_t)F.half, gflag, Linv, Uinv, inv_red, kchunk, He, Hd, Pd,
-                                (int)pdn, Pe, (int)pem);
+                                (int)pdn, Pe, (int)pem, (int)diag0);
     } else {
         FFP_SEL(FFP_L64)
     }

@@ -436,6 +436,8 @@ __global__ void k_iota(int32_t *__restrict__ v, int64_t n) {
         v[i] = (int32_t)i;
 }
 
+__global__ void k_set_int(int *dst, int v) { *dst = v; }
+
 static int iota(int32_t *v, int64_t n, hipStream_t s) {
     if (n <= 0) return FFP_OK;
     unsigned g = (unsigned)((n + 255) / 256);
@@ -518,6 +520,7 @@ struct Ctx {
     hipStream_t s;
     int64_t *rank_dev;   // device address of a pinned host word the leaves write their rank to
     int64_t *rank_host;  // the same word for the host
+    int *flag_dev;       // device word: generic-attempt flag, zero-block flag
 };
 
 int read_rank(const Ctx &c, int64_t *out) {
@@ -606,7 +609,47 @@ bool make_seg(SegPerm &sp, const int64_t (*segs)[2], int nseg, int64_t lo, int64
     return !ident;
 }
 
-int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q, int64_t *rank) {
+}  // namespace
+int try_generic(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, bool *ok, int64_t *k0);
+int read_flag(const Ctx &c, int64_t *out);
+namespace {
+
+// any nonzero entry in an m x n block: *flag |= 1 (entries are canonical)
+__global__ __launch_bounds__(256) void k_any_nonzero(int64_t m, int64_t n, const int32_t *__restrict__ A, int64_t lda,
+                                                     int *__restrict__ flag) {
+    bool nz = false;
+    for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
+        const int32_t *row = A + i * lda;
+        for (int64_t j = threadIdx.x; j < n; j += 256) nz |= row[j] != 0;
+    }
+    if (__syncthreads_or(nz) && threadIdx.x == 0) atomicOr(flag, 1);
+}
+
+// A sub-block of a rank-deficient input is often zero (its rank spent
+// above): one reduction and one read-back then replace its whole
+// recursion (every leaf of which would read a rank back).
+constexpr int64_t kZeroCheckMin = 128 * 128;
+
+int block_is_zero(Ctx &c, int64_t m, int64_t n, const int32_t *A, int64_t lda, bool *zero) {
+    *zero = false;
+    if (m * n < kZeroCheckMin) return FFP_OK;
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, c.s, c.flag_dev, 0);
+    const unsigned g = (unsigned)(m < 1024 ? m : 1024);
+    hipLaunchKernelGGL(k_any_nonzero, dim3(g), dim3(256), 0, c.s, m, n, A, lda, c.flag_dev);
+    FFP_HIP_CHECK(hipGetLastError());
+    int64_t f = 0;
+    FFP_CHECK(read_flag(c, &f));
+    *zero = f == 0;
+    return FFP_OK;
+}
+
+int pluq_sub(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q, int64_t *rank);
+
+// gen_ok: every leading minor of this block up to that order is known to be
+// nonzero (from a failed generic attempt on a block with the same top-left
+// corner); a leading tile within that order is then factored as a plain LU.
+int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q, int64_t *rank,
+             int64_t gen_ok) {
     hipStream_t s = c.s;
     Arena &ws = *c.ws;
     if (m == 0 || n == 0) {
@@ -632,9 +675,21 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
         return read_rank(c, rank);
     }
     const int64_t m1 = m / 2, n1 = n / 2;
-    // ---- 1. top-left tile
+    // ---- 1. top-left tile (same corner: same leading minors)
     int64_t r1 = 0;
-    FFP_CHECK(pluq_rec(c, m1, n1, A, lda, P, Q, &r1));
+    {
+        const int64_t k1 = m1 < n1 ? m1 : n1;
+        bool gen = false;
+        int64_t k0 = 0;
+        if (k1 > 64 && k1 <= gen_ok) FFP_CHECK(try_generic(c, m1, n1, A, lda, &gen, &k0));
+        if (gen) {
+            FFP_CHECK(iota(P, m1, s));
+            FFP_CHECK(iota(Q, n1, s));
+            r1 = k1;
+        } else {
+            FFP_CHECK(pluq_rec(c, m1, n1, A, lda, P, Q, &r1, gen_ok));
+        }
+    }
     // ---- 2. [B1; B2] = P1^T A2,  [C1 C2] = A3 Q1^T
     FFP_CHECK(rows_perm(c, m1, n - n1, A + n1, lda, P));
     FFP_CHECK(cols_perm(c, m - m1, n1, A + m1 * lda, lda, Q));
@@ -649,8 +704,8 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
     if ((!P2 && m1 - r1 > 0) || (!Q2 && n - n1 > 0) || (!P3 && m - m1 > 0) || (!Q3 && n1 - r1 > 0))
         return FFP_E_WORKSPACE;
     int64_t r2 = 0, r3 = 0;
-    FFP_CHECK(pluq_rec(c, m1 - r1, n - n1, A + r1 * lda + n1, lda, P2, Q2, &r2));
-    FFP_CHECK(pluq_rec(c, m - m1, n1 - r1, A + m1 * lda + r1, lda, P3, Q3, &r3));
+    FFP_CHECK(pluq_sub(c, m1 - r1, n - n1, A + r1 * lda + n1, lda, P2, Q2, &r2));
+    FFP_CHECK(pluq_sub(c, m - m1, n1 - r1, A + m1 * lda + r1, lda, P3, Q3, &r3));
     // ---- 5. carry the sub-permutations to the rest of their rows / columns
     if (r1 > 0) {
         FFP_CHECK(rows_perm(c, m1 - r1, r1, A + r1 * lda, lda, P2));                 // M1
@@ -674,7 +729,7 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
     int32_t *Q4 = (int32_t *)ws.take((size_t)(n - n1 - r2) * 4);
     if ((!P4 && m - m1 - r3 > 0) || (!Q4 && n - n1 - r2 > 0)) return FFP_E_WORKSPACE;
     int64_t r4 = 0;
-    FFP_CHECK(pluq_rec(c, m - m1 - r3, n - n1 - r2, R, lda, P4, Q4, &r4));
+    FFP_CHECK(pluq_sub(c, m - m1 - r3, n - n1 - r2, R, lda, P4, Q4, &r4));
     FFP_CHECK(rows_perm(c, m - m1 - r3, n1 + r2, A + (m1 + r3) * lda, lda, P4));
     FFP_CHECK(cols_perm(c, m1 + r3, n - n1 - r2, A + n1 + r2, lda, Q4));
     // ---- 8. final rotations: rows [a f f' g R r'] -> [a f g R f' r'],
@@ -715,6 +770,19 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
     *rank = r1 + r2 + r3 + r4;
     return FFP_OK;
 }
+
+// F, G and R of a node: a zero block is factored by its identity permutations
+int pluq_sub(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q, int64_t *rank) {
+    bool zero = false;
+    if (m > 0 && n > 0) FFP_CHECK(block_is_zero(c, m, n, A, lda, &zero));
+    if (zero) {
+        FFP_CHECK(iota(P, m, c.s));
+        FFP_CHECK(iota(Q, n, c.s));
+        *rank = 0;
+        return FFP_OK;
+    }
+    return pluq_rec(c, m, n, A, lda, P, Q, rank, 0);
+}
 }  // namespace
 
 // ---------------------------------------------------------------- generic speculation
@@ -746,27 +814,28 @@ int node_updates_gen(Ctx &c, int64_t m, int64_t n, int64_t h, int32_t *A, int64_
 }
 
 // Li / Ui: block-inverse slots from this block's diagonal offset on
-int lu_generic(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int *gflag, double *Li, double *Ui) {
+int lu_generic(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int *gflag, double *Li, double *Ui,
+               int64_t d0) {
     if (m == 0 || n == 0) return FFP_OK;
-    if (leaf64_fits(m, n)) return leaf64_launch(*c.F, m, n, A, lda, nullptr, nullptr, nullptr, gflag, Li, Ui, c.s);
+    if (leaf64_fits(m, n))
+        return leaf64_launch(*c.F, m, n, A, lda, nullptr, nullptr, nullptr, gflag, Li, Ui, c.s, nullptr, nullptr,
+                             nullptr, 0, nullptr, 0, d0);
     const int64_t k = m < n ? m : n;
     const int64_t h = k <= 64 ? k : 64 * ((k + 127) / 128);
     if (h == 64 && m <= 128 && n <= 128 && c.F->kexact >= 64) {
         // both halves are leaves: the node's two solves run at the end of the
         // first leaf and its update H = A4 - E D at the start of the second
         FFP_CHECK(leaf64_launch(*c.F, 64, 64, A, lda, nullptr, nullptr, nullptr, gflag, Li, Ui, c.s, nullptr,
-                                nullptr, A + 64, n - 64, A + 64 * lda, m - 64));
+                                nullptr, A + 64, n - 64, A + 64 * lda, m - 64, d0));
         return leaf64_launch(*c.F, m - 64, n - 64, A + 64 * lda + 64, lda, nullptr, nullptr, nullptr, gflag,
-                             Li + kBlk, Ui + kBlk, c.s, A + 64 * lda, A + 64);
+                             Li + kBlk, Ui + kBlk, c.s, A + 64 * lda, A + 64, nullptr, 0, nullptr, 0, d0 + 64);
     }
-    FFP_CHECK(lu_generic(c, h, h, A, lda, gflag, Li, Ui));
+    FFP_CHECK(lu_generic(c, h, h, A, lda, gflag, Li, Ui, d0));
     FFP_CHECK(node_updates_gen(c, m, n, h, A, lda, Li, Ui));
     const int64_t off = (h / 64) * kBlk;  // h is a multiple of 64 whenever the rest is non-empty
-    return lu_generic(c, m - h, n - h, A + h * lda + h, lda, gflag, Li + off, Ui + off);
+    return lu_generic(c, m - h, n - h, A + h * lda + h, lda, gflag, Li + off, Ui + off, d0 + h);
 }
 }  // namespace
-
-__global__ void k_set_int(int *dst, int v) { *dst = v; }
 
 size_t pluq_ws(int64_t m, int64_t n, const Field &F, int path) {
     // largest out-of-place permutation (the whole block) + index arrays along
@@ -786,9 +855,49 @@ size_t pluq_ws(int64_t m, int64_t n, const Field &F, int path) {
     return b;
 }
 
+// Flag words through the pinned host word: one small copy kernel, one
+// stream synchronisation.
+__global__ void k_flag_to_word(const int *flag, int64_t *word) { *word = *flag; }
+int read_flag(const Ctx &c, int64_t *out) {
+    hipLaunchKernelGGL(k_flag_to_word, dim3(1), dim3(1), 0, c.s, c.flag_dev, c.rank_dev);
+    FFP_HIP_CHECK(hipGetLastError());
+    return read_rank(c, out);
+}
+
+// The generic attempt on an m x n block (a copy kept to fall back): *ok when
+// every pivot was nonzero (A then holds the LU factors, P = Q = identity);
+// otherwise A is restored and *k0 receives the order of the first vanishing
+// leading minor minus one (all leading minors up to order k0 are nonzero).
+int try_generic(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, bool *ok, int64_t *k0) {
+    Arena &ws = *c.ws;
+    hipStream_t s = c.s;
+    const size_t mk = ws.mark();
+    int32_t *backup = (int32_t *)ws.take((size_t)m * (size_t)n * 4);
+    const size_t nblk = (size_t)(((m < n ? m : n) + 63) / 64);
+    double *Li = (double *)ws.take(nblk * kBlk * sizeof(double));
+    double *Ui = (double *)ws.take(nblk * kBlk * sizeof(double));
+    if (!backup || !Li || !Ui) return FFP_E_WORKSPACE;
+    FFP_CHECK(copy2d(m, n, A, lda, backup, n, s));
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c.flag_dev, 0);
+    FFP_HIP_CHECK(hipGetLastError());
+    FFP_CHECK(lu_generic(c, m, n, A, lda, c.flag_dev, Li, Ui, 0));
+    int64_t flag = 0;
+    FFP_CHECK(read_flag(c, &flag));
+    *ok = flag == 0;
+    *k0 = flag - 1;
+    if (!*ok) FFP_CHECK(copy2d(m, n, backup, n, A, lda, s));
+    ws.release(mk);
+    // leaves only ever write 1 + a diagonal index: anything else is an internal error
+    if (flag < 0 || flag > (m < n ? m : n)) {
+        FFP_HIP_CHECK(hipStreamSynchronize(s));
+        return FFP_E_INTERNAL;
+    }
+    return FFP_OK;
+}
+
 int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
              int64_t *r, Arena &ws, hipStream_t s) {
-    int64_t *flag_dev = (int64_t *)ws.take(256);
+    int *flag_dev = (int *)ws.take(256);
     if (!flag_dev) return FFP_E_WORKSPACE;
     RankWord rw;
     FFP_CHECK(rank_word_get(&rw));
@@ -796,44 +905,20 @@ int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t
         RankWord w;
         ~WordBack() { rank_word_put(w); }
     } word_back{rw};
-    Ctx c{path, &F, &ws, s, rw.dev, rw.host};
+    Ctx c{path, &F, &ws, s, rw.dev, rw.host, flag_dev};
+    int64_t gen_ok = 0;
     if (m > 64 && n > 64 && !getenv("FFP_PLUQ_GENERAL_ONLY")) {
-        // speculate that A has generic rank profile (keep a copy to fall back)
-        const size_t mk = ws.mark();
-        int32_t *backup = (int32_t *)ws.take((size_t)m * (size_t)n * 4);
-        const size_t nblk = (size_t)(((m < n ? m : n) + 63) / 64);
-        double *Li = (double *)ws.take(nblk * kBlk * sizeof(double));
-        double *Ui = (double *)ws.take(nblk * kBlk * sizeof(double));
-        int *gflag = (int *)flag_dev;
-        if (!backup || !Li || !Ui) return FFP_E_WORKSPACE;
-        FFP_CHECK(copy2d(m, n, A, lda, backup, n, s));
-        hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, gflag, 0);
-        FFP_HIP_CHECK(hipGetLastError());
-        FFP_CHECK(lu_generic(c, m, n, A, lda, gflag, Li, Ui));
-        int64_t flag = 0;
-        {
-            std::lock_guard<std::mutex> g(g_pin_mu);
-            if (!g_pin) FFP_HIP_CHECK(hipHostMalloc((void **)&g_pin, 64, hipHostMallocDefault));
-            FFP_HIP_CHECK(hipMemcpyAsync(g_pin, gflag, sizeof(int), hipMemcpyDeviceToHost, s));
-            FFP_HIP_CHECK(hipStreamSynchronize(s));
-            flag = *(int *)g_pin;
-        }
-        if (flag == 0) {
+        // speculate that A has generic rank profile
+        bool ok = false;
+        FFP_CHECK(try_generic(c, m, n, A, lda, &ok, &gen_ok));
+        if (ok) {
             FFP_CHECK(iota(P, m, s));
             FFP_CHECK(iota(Q, n, s));
             *r = m < n ? m : n;
-            ws.release(mk);
             return FFP_OK;
         }
-        FFP_CHECK(copy2d(m, n, backup, n, A, lda, s));
-        ws.release(mk);
-        if (flag != 1) {
-            // leaves only ever write 1: any other value is an internal error
-            FFP_HIP_CHECK(hipStreamSynchronize(s));
-            return FFP_E_INTERNAL;
-        }
     }
-    return pluq_rec(c, m, n, A, lda, P, Q, r);
+    return pluq_rec(c, m, n, A, lda, P, Q, r, gen_ok);
 }
 
 // ===================================================================== rank profiles
