@@ -11,6 +11,8 @@
 // at depth d) and read with uniform lane indices, so the walk runs on the
 // scalar unit.  The pivot search is one ballot, the inverse one extended
 // Euclid on the pivot.
+#include <type_traits>
+
 #include "ffp_internal.hpp"
 #include "ffp_device.hpp"
 #include "trinv.hpp"
@@ -324,7 +326,10 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
 // Entries are brought back to |W| <= (p-1)/2 + 3 every step (rounded
 // quotient), so q W - a u stays below 2^53 for every p the FP64 embedding
 // takes, and a pivot is zero mod p exactly when it is 0.0.  SMALLP selects
-// the inverse routine.  A zero pivot sets *gflag to 1 + its index on the
+// the inverse routine.  LAZY (4 (half + 3)^3 < 2^53): the rows below a block
+// of pivots are reduced every second step only; one unreduced step leaves
+// |x| <= 2 B^2 (B = half + 3 bounds every reduced entry), the next one
+// <= 4 B^3, and every product in both steps is an exact integer below 2^53.  A zero pivot sets *gflag to 1 + its index on the
 // whole diagonal (diag0 = the block's offset there) and leaves A untouched
 // (A is written only at the end); nothing runs once *gflag is set.
 // With Linv / Uinv non-null the leaf also stores L^-1 and U^-1 of its k x k
@@ -337,7 +342,7 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
 //  - Pd / Pe non-null (needs Linv): after the factorisation the 64 x pdn
 //    panel right of the block becomes L^-1 Pd and the pem x 64 panel below
 //    it Pe U^-1 (the two solves of the node).
-template <bool SMALLP, int NW>
+template <bool SMALLP, int NW, bool LAZY>
 __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *__restrict__ A, int64_t lda,
                                                       double p, double pinv, int32_t half, int *__restrict__ gflag,
                                                       double *__restrict__ Linv, double *__restrict__ Uinv,
@@ -421,6 +426,7 @@ __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *_
         const double a = rld(x, k);
         return mod_near(fma(-a, um, q * x), p, pinv);
     };
+    auto step_raw = [&](double x, double um, double q, int k) { return fma(-rld(x, k), um, q * x); };
     // blocks of KB steps: rows kb .. kb + KB - 1 are rows e = kb / NW of waves
     // kb % NW .. kb % NW + KB - 1 (KB divides NW)
 #pragma unroll
@@ -458,24 +464,35 @@ __global__ __launch_bounds__(64 * NW) void k_leaf_gen(int mb, int nb, int32_t *_
             qv[kb + tid] = qt;
         }
         // own rows: below the block, KB steps; in the block, the final pivot row
+        // (copies of the row loop for full blocks and the last partial one: a
+        // uniform branch per block, none per row)
+        auto own_rows = [&](auto lazy_c, auto full_c) {
+            constexpr bool LZ = decltype(lazy_c)::value, FULL = decltype(full_c)::value;
+            const int nbr = FULL ? KB : nbk;
 #pragma unroll
-        for (int e = eb; e < RPW; ++e) {
-            const bool inblk = e == eb && wave >= w0 && wave < w0 + nbk;
-            const bool below = e > eb || wave >= w0 + nbk;  // rows after the block's pivots
-            if (inblk) {
-                const int j = wave - w0;
-                double ut = u[0];
+            for (int e = eb; e < RPW; ++e) {
+                const bool inblk = e == eb && wave >= w0 && wave < w0 + nbr;
+                const bool below = e > eb || wave >= w0 + nbr;  // rows after the block's pivots
+                if (inblk) {
+                    const int j = wave - w0;
+                    double ut = u[0];
 #pragma unroll
-                for (int jj = 1; jj < KB; ++jj) ut = j == jj ? u[jj] : ut;
-                R[e] = ut;
-            } else if (below) {
-                double x = R[e];
+                    for (int jj = 1; jj < KB; ++jj) ut = j == jj ? u[jj] : ut;
+                    R[e] = ut;
+                } else if (below) {
+                    double x = R[e];
 #pragma unroll
-                for (int j = 0; j < KB; ++j)
-                    if (j < nbk) x = step(x, um[j], q[j], kb + j);
-                R[e] = x;
+                    for (int j = 0; j < KB; ++j) {
+                        if (LZ) x = (j & 1) == 0 ? step_raw(x, um[j], q[j], kb + j) : step(x, um[j], q[j], kb + j);
+                        else if (FULL || j < nbk) x = step(x, um[j], q[j], kb + j);
+                    }
+                    R[e] = x;
+                }
             }
-        }
+        };
+        // a full block (KB even) ends on a reducing step
+        if (nbk == KB) own_rows(std::integral_constant<bool, LAZY>{}, std::true_type{});
+        else own_rows(std::false_type{}, std::false_type{});
         }
     }
     __syncthreads();
@@ -621,12 +638,17 @@ int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda,
         if ((He || Pd) && (F.kexact < 64 || (Pd && (!Linv || m != 64 || n != 64 || pdn > 64 || pem > 64)) ||
                            (He && (!Hd || m > 64 || n > 64))))
             return FFP_E_INTERNAL;
-        if (small) hipLaunchKernelGGL((k_leaf_gen<true, kGenWaves>), dim3(1), dim3(64 * kGenWaves), 0, s, (int)m, (int)n, A,
-                                      lda, F.pd, F.pinv, (int32_t)F.half, gflag, Linv, Uinv, inv_red, kchunk, He, Hd,
-                                      Pd, (int)pdn, Pe, (int)pem, (int)diag0);
-        else hipLaunchKernelGGL((k_leaf_gen<false, kGenWaves>), dim3(1), dim3(64 * kGenWaves), 0, s, (int)m, (int)n, A,
-                                lda, F.pd, F.pinv, (int32_t)F.half, gflag, Linv, Uinv, inv_red, kchunk, He, Hd, Pd,
-                                (int)pdn, Pe, (int)pem, (int)diag0);
+        // two unreduced steps stay exact: 4 B^3 < 2^53 with B = half + 3
+        const double B = (double)F.half + 3.0;
+        const bool lazy = 4.0 * B * B * B < 9007199254740992.0;
+#define FFP_LG(S_, L_)                                                                                              \
+    hipLaunchKernelGGL((k_leaf_gen<S_, kGenWaves, L_>), dim3(1), dim3(64 * kGenWaves), 0, s, (int)m, (int)n, A, lda, \
+                       F.pd, F.pinv, (int32_t)F.half, gflag, Linv, Uinv, inv_red, kchunk, He, Hd, Pd, (int)pdn, Pe,   \
+                       (int)pem, (int)diag0)
+        if (lazy) FFP_LG(true, true);
+        else if (small) FFP_LG(true, false);
+        else FFP_LG(false, false);
+#undef FFP_LG
     } else {
         FFP_SEL(FFP_L64)
     }

@@ -274,3 +274,23 @@ def test_pluq_general_path_on_generic_inputs(lib, orc):
         finally:
             del os.environ["FFP_PLUQ_GENERAL_ONLY"]
         _pluq_compare(lib, orc, A, p, 0, "speculative")
+
+
+def test_pluq_generic_prefix_shortcuts(lib, orc):
+    """Rank-deficient inputs whose leading minors are nonzero up to some order
+    k0: the failed generic attempt's k0 lets leading tiles within that order
+    factor as plain LU, and zero sub-blocks skip their recursion.  Cases: the
+    shortcut at the top node's tile, one level down, with a nonzero Schur
+    complement after it, and a full-rank input whose first vanishing minor is
+    planted at order 200 (the rest of the recursion is the general one)."""
+    p = 131071
+    rng = np.random.default_rng(77)
+    cases = [("lowrank 1024 r300", wl.lowrank(1024, 1024, 300, p, 701)),
+             ("lowrank 600 r450", wl.lowrank(600, 600, 450, p, 702)),
+             ("lowrank 700x900 r500", wl.lowrank(700, 900, 500, p, 703))]
+    B = rng.integers(0, p, (640, 640)).astype(np.int32)
+    B[:200, :200] = wl.lowrank(200, 200, 199, p, 704)
+    cases.append(("planted minor 200", B))
+    for tag, A in cases:
+        for path in paths_for(p):
+            _pluq_compare(lib, orc, A, p, path, tag)
