@@ -195,7 +195,11 @@ constexpr int kTBB = 256;  // fused base case: up to four 64-blocks
 //   transposed (right).
 constexpr int kVB = 16;  // vectors per workgroup of the fused base case
 
-template <bool LEFT, bool RED>
+// NBT > 0: d == 64 NBT and T's rows are 16-byte aligned (host-checked), so
+// that the item count and every load's form are compile-time: no branch
+// between a fragment load and its use, and the loads of several items stay in
+// flight together (a branch join makes the wait conservative).
+template <bool LEFT, bool RED, int NBT = 0>
 __device__ __forceinline__ void trsm_blk_body(int bid, int d, int64_t nv, const int32_t *__restrict__ T,
                                               int64_t ldt, int direct, int fwd, const double *__restrict__ W,
                                               int32_t *__restrict__ B, int64_t ldb, double p, double pinv,
@@ -205,29 +209,9 @@ __device__ __forceinline__ void trsm_blk_body(int bid, int d, int64_t nv, const 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, k4 = lane >> 4;
     const int64_t v0 = (int64_t)bid * kVB;
-    const int nb = (d + kTB - 1) / kTB;
+    const int nb = NBT > 0 ? NBT : (d + kTB - 1) / kTB;
     const double hd = (double)half;
     const int32_t ip = (int32_t)p;
-    // ---- slab in (clamped loads, zero outside)
-    {
-        constexpr int PER = kTBB * kVB / 256;
-        int32_t v[PER];
-#pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int idx = tid + e * 256;
-            const int c = LEFT ? idx / kVB : idx % kTBB, w = LEFT ? idx % kVB : idx / kTBB;
-            const int cc = c < d ? c : d - 1;
-            const int64_t vv = v0 + w < nv ? v0 + w : nv - 1;
-            v[e] = LEFT ? B[(int64_t)cc * ldb + vv] : B[vv * ldb + cc];
-        }
-#pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int idx = tid + e * 256;
-            const int c = LEFT ? idx / kVB : idx % kTBB, w = LEFT ? idx % kVB : idx / kTBB;
-            const int32_t x = (c < d && v0 + w < nv) ? v[e] : 0;
-            S[c][w] = x > half ? x - ip : x;
-        }
-    }
     // items: for q = 0.., the sources r < q then the inverse of block q
     const int nitems = nb * (nb + 1) / 2;
     auto item = [&](int it, int &q, int &r) {
@@ -241,7 +225,7 @@ __device__ __forceinline__ void trsm_blk_body(int bid, int d, int64_t nv, const 
     // any order as long as the S operand uses the same one), so that each
     // lane reads 16 consecutive entries of a row of T or W
     const int arow = 16 * wave + r16;
-    const bool vec = (((uintptr_t)T | (uintptr_t)(ldt * 4)) & 15) == 0;
+    const bool vec = NBT > 0 || (((uintptr_t)T | (uintptr_t)(ldt * 4)) & 15) == 0;
     // operand fragments in flight: a ring of PD raw slots (16 int32 entries
     // of T, or 16 doubles of W as 32 words), filled PD items ahead so that
     // several global reads overlap the products
@@ -257,7 +241,7 @@ __device__ __forceinline__ void trsm_blk_body(int bid, int d, int64_t nv, const 
             if (direct) {
                 const int a = 64 * t + arow, b0 = 64 * sb + 16 * k4;
                 const int32_t *row = T + (int64_t)(a < d ? a : d - 1) * ldt;
-                if (vec && b0 + KS <= d) {
+                if (NBT > 0 || (vec && b0 + KS <= d)) {
 #pragma unroll
                     for (int v = 0; v < KS / 4; ++v) {
                         const uint4 x = *(const uint4 *)(row + b0 + 4 * v);
@@ -327,6 +311,27 @@ __device__ __forceinline__ void trsm_blk_body(int bid, int d, int64_t nv, const 
 #pragma unroll
     for (int j = 0; j < PD; ++j)
         if (j < nitems) prefetch(j, ring[j]);
+    // (the slab's loads go out after the first operands': one wait covers both)
+    // ---- slab in (clamped loads, zero outside)
+    {
+        constexpr int PER = kTBB * kVB / 256;
+        int32_t v[PER];
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * 256;
+            const int c = LEFT ? idx / kVB : idx % kTBB, w = LEFT ? idx % kVB : idx / kTBB;
+            const int cc = c < d ? c : d - 1;
+            const int64_t vv = v0 + w < nv ? v0 + w : nv - 1;
+            v[e] = LEFT ? B[(int64_t)cc * ldb + vv] : B[vv * ldb + cc];
+        }
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int idx = tid + e * 256;
+            const int c = LEFT ? idx / kVB : idx % kTBB, w = LEFT ? idx % kVB : idx / kTBB;
+            const int32_t x = (c < d && v0 + w < nv) ? v[e] : 0;
+            S[c][w] = x > half ? x - ip : x;
+        }
+    }
     __syncthreads();
     auto run_item = [&](int it, uint32_t(&sl)[2 * KS]) {
         int q, r;
@@ -412,14 +417,15 @@ __global__ __launch_bounds__(256) void k_trsm_apply_pair(int h, int gd, int64_t 
     if ((int)blockIdx.x < gd) trsm_apply_body<true, RED>(blockIdx.x, h, nvd, Li, Bd, ldb, p, pinv, half, ksteps);
     else trsm_apply_body<false, RED>(blockIdx.x - gd, h, nve, Ui, Be, ldb, p, pinv, half, ksteps);
 }
-template <bool RED>
+template <bool RED, int NBT>
 __global__ __launch_bounds__(256) void k_trsm_blk_pair(int h, int gd, int64_t nvd, int32_t *__restrict__ Bd,
                                                        int64_t nve, int32_t *__restrict__ Be, int64_t ldb,
                                                        const int32_t *__restrict__ T, int64_t ldt,
                                                        const double *__restrict__ Li, const double *__restrict__ Ui,
                                                        double p, double pinv, int32_t half, int ksteps) {
-    if ((int)blockIdx.x < gd) trsm_blk_body<true, RED>(blockIdx.x, h, nvd, T, ldt, 1, 1, Li, Bd, ldb, p, pinv, half, ksteps);
-    else trsm_blk_body<false, RED>(blockIdx.x - gd, h, nve, T, ldt, 0, 1, Ui, Be, ldb, p, pinv, half, ksteps);
+    if ((int)blockIdx.x < gd)
+        trsm_blk_body<true, RED, NBT>(blockIdx.x, h, nvd, T, ldt, 1, 1, Li, Bd, ldb, p, pinv, half, ksteps);
+    else trsm_blk_body<false, RED, NBT>(blockIdx.x - gd, h, nve, T, ldt, 0, 1, Ui, Be, ldb, p, pinv, half, ksteps);
 }
 
 static int trsm_blk(const Field &F, int side, int d, int64_t nv, const int32_t *T, int64_t ldt, bool direct,
@@ -569,11 +575,22 @@ static int trsm_pair_base(const Field &F, int64_t h, const int32_t *T, int64_t l
     } else {
         const bool red = F.kexact < kTB;
         const int gd = (int)((nvd + kVB - 1) / kVB), ge = (int)((nve + kVB - 1) / kVB);
-#define FFP_BP(R_)                                                                                          \
-    hipLaunchKernelGGL((k_trsm_blk_pair<R_>), dim3((unsigned)(gd + ge)), dim3(256), 0, s, (int)h, gd, nvd, Bd, nve, \
-                       Be, ldb, T, ldt, Li, Ui, F.pd, F.pinv, (int32_t)F.half, ksteps)
-        if (red) FFP_BP(true);
-        else FFP_BP(false);
+        // whole 64-blocks and aligned rows: the item count is a template argument
+        const bool aligned = (((uintptr_t)T | (uintptr_t)(ldt * 4)) & 15) == 0;
+        const int nbt = (aligned && h % kTB == 0) ? (int)(h / kTB) : 0;
+#define FFP_BP(R_, N_)                                                                                          \
+    hipLaunchKernelGGL((k_trsm_blk_pair<R_, N_>), dim3((unsigned)(gd + ge)), dim3(256), 0, s, (int)h, gd, nvd, Bd, \
+                       nve, Be, ldb, T, ldt, Li, Ui, F.pd, F.pinv, (int32_t)F.half, ksteps)
+#define FFP_BPN(R_)                   \
+    switch (nbt) {                    \
+        case 2: FFP_BP(R_, 2); break; \
+        case 3: FFP_BP(R_, 3); break; \
+        case 4: FFP_BP(R_, 4); break; \
+        default: FFP_BP(R_, 0); break; \
+    }
+        if (red) FFP_BPN(true)
+        else FFP_BPN(false)
+#undef FFP_BPN
 #undef FFP_BP
     }
     FFP_HIP_CHECK(hipGetLastError());
