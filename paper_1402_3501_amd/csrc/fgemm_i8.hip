@@ -17,7 +17,10 @@
 // 16-byte MFMA operand is one contiguous load); the product kernel computes
 // a 128 x 128 block of C per workgroup, streaming 64-deep K tiles of all L
 // digit planes of both operands through LDS (double buffered) into 8 wave64s,
-// each owning a 32 x 64 sub-block.
+// each owning a 32 x 64 sub-block.  Products with too few output blocks to
+// fill the chip split K over several workgroups per block (each writes its
+// reduced partial result, a second kernel sums them mod p and applies alpha
+// and beta).
 #include "ffp_internal.hpp"
 #include "ffp_device.hpp"
 
@@ -27,6 +30,9 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kI8BM = 128, kI8BN = 128, kI8BK = 64;
 constexpr int kI8Threads = 512;
+// split-K: at most 4 parts, partial results at most 32 MiB
+constexpr int kI8MaxSplit = 4;
+constexpr int64_t kI8SplitBytes = (int64_t)32 << 20;
 
 static inline int64_t rup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -108,7 +114,8 @@ __global__ __launch_bounds__(kI8Threads) void k_fgemm_i8(const int8_t *__restric
                                                         int64_t Kp, int64_t planeA, int64_t planeB, int64_t m,
                                                         int64_t n, int32_t *__restrict__ C, int64_t ldc, double p,
                                                         double pinv, double alpha, double beta, double w1,
-                                                        double w2, double w3, double w4, int ntx, int nty) {
+                                                        double w2, double w3, double w4, int ntx, int nty,
+                                                        int64_t kt_per, int32_t *__restrict__ part) {
     constexpr int NS = 2 * L - 1;        // shift classes
     constexpr int BM = kI8BM, BN = kI8BN, BK = kI8BK;
     constexpr int ROW = BK + 16;         // padded LDS row (bytes)
@@ -119,8 +126,12 @@ __global__ __launch_bounds__(kI8Threads) void k_fgemm_i8(const int8_t *__restric
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+    // part != nullptr: workgroup b computes K tiles [kt_per z, kt_per (z + 1))
+    // of output block b % (ntx nty), z = b / (ntx nty), into part[z] (m x n)
+    const int tiles = ntx * nty;
+    const int z = part ? (int)blockIdx.x / tiles : 0;
     int ty, tx;
-    xcd_tile(blockIdx.x, ntx, nty, ty, tx);
+    xcd_tile(part ? (int)blockIdx.x % tiles : (int)blockIdx.x, ntx, nty, ty, tx);
     const int64_t m0 = (int64_t)ty * BM, n0 = (int64_t)tx * BN;
 
     // global -> register staging: L*(BM+BN)*BK/16 chunks of 16 bytes
@@ -164,13 +175,14 @@ __global__ __launch_bounds__(kI8Threads) void k_fgemm_i8(const int8_t *__restric
 #pragma unroll
             for (int j = 0; j < FN; ++j) acc[s][i][j] = v4i{0, 0, 0, 0};
 
-    const int64_t nt = Kp / BK;
-    load(0);
+    const int64_t t0 = part ? kt_per * z : 0;
+    const int64_t nt = part ? ((Kp / BK - t0) < kt_per ? Kp / BK - t0 : kt_per) : Kp / BK;
+    load(t0 * BK);
     store(0);
     __syncthreads();
     for (int64_t t = 0; t < nt; ++t) {
         const int buf = (int)(t & 1);
-        if (t + 1 < nt) load((t + 1) * BK);
+        if (t + 1 < nt) load((t0 + t + 1) * BK);
         const int kq = (lane >> 4) * 16, r = lane & 15;
         v4i a[L][FM];
 #pragma unroll
@@ -210,6 +222,10 @@ __global__ __launch_bounds__(kI8Threads) void k_fgemm_i8(const int8_t *__restric
 #pragma unroll
                     for (int s = 0; s < NS; ++s) t = fma(mod_near((double)acc[s][i][j][v], p, pinv), w[s], t);
                     double rres = mod_canon(t, p, pinv);
+                    if (part) {
+                        part[((int64_t)z * m + gi) * n + gj] = (int32_t)rres;
+                        continue;
+                    }
                     if (alpha != 1.0) rres = mod_canon(alpha * rres, p, pinv);
                     if (beta != 0.0) {
                         double c = (double)C[gi * ldc + gj];
@@ -224,6 +240,27 @@ __global__ __launch_bounds__(kI8Threads) void k_fgemm_i8(const int8_t *__restric
     }
 }
 
+// C <- alpha * (sum of the nz partial results) + beta * C, all mod p (each
+// partial is canonical, the sum of at most kI8MaxSplit of them is exact)
+__global__ __launch_bounds__(256) void k_i8_combine(int64_t m, int64_t n, int nz, const int32_t *__restrict__ part,
+                                                    int32_t *__restrict__ C, int64_t ldc, double p, double pinv,
+                                                    double alpha, double beta) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= m * n) return;
+    const int64_t gi = idx / n, gj = idx % n;
+    double t = 0.0;
+    for (int zz = 0; zz < nz; ++zz) t += (double)part[(int64_t)zz * m * n + idx];
+    double rres = mod_canon(t, p, pinv);
+    if (alpha != 1.0) rres = mod_canon(alpha * rres, p, pinv);
+    if (beta != 0.0) {
+        double c = (double)C[gi * ldc + gj];
+        if (beta != 1.0) c = mod_canon(beta * c, p, pinv);
+        rres += c;
+        if (rres >= p) rres -= p;
+    }
+    C[gi * ldc + gj] = (int32_t)rres;
+}
+
 // ------------------------------------------------------------------ host side
 static int64_t kchunk_for(int L) { return L == 1 ? 131072 : (L == 2 ? 65536 : 32768); }
 
@@ -231,7 +268,20 @@ size_t fgemm_i8_ws(const Field &F, int64_t m, int64_t n, int64_t k) {
     const int L = F.limbs > 0 ? F.limbs : 3;
     const int64_t kc = k < kchunk_for(L) ? k : kchunk_for(L);
     const int64_t Kp = rup(kc > 0 ? kc : 1, kI8BK);
-    return (size_t)L * (size_t)(rup(m, kI8BM) + rup(n, kI8BN)) * (size_t)Kp + 1024;
+    const int64_t Mp = rup(m, kI8BM), Np = rup(n, kI8BN);
+    const int64_t split = (int64_t)kI8MaxSplit * Mp * Np * 4 < kI8SplitBytes ? (int64_t)kI8MaxSplit * Mp * Np * 4
+                                                                            : kI8SplitBytes;
+    return (size_t)L * (size_t)(Mp + Np) * (size_t)Kp + (size_t)split + 1280;
+}
+
+// K parts for a product of `tiles` output blocks and nt K tiles: enough to
+// bring the grid to the chip's 256 compute units, each part at least 4 K
+// tiles, the partial results within kI8SplitBytes
+static int i8_split(int64_t tiles, int64_t nt, int64_t m, int64_t n) {
+    int z = 1;
+    while (z < kI8MaxSplit && tiles * z * 2 <= 256 && nt / (z * 2) >= 4 && (int64_t)(z * 2) * m * n * 4 <= kI8SplitBytes)
+        z *= 2;
+    return z;
 }
 
 template <int L>
@@ -265,14 +315,23 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
         hipLaunchKernelGGL((k_split<L>), dim3((unsigned)(Kp / 64), (unsigned)((Mp + Np) / 64)), dim3(256), 0, s, sa,
                            sb, Mp / 64, kc, Kp, (int32_t)F.half, (int32_t)F.p);
         const double be = kc0 == 0 ? (double)beta : 1.0;
+        const int ntx = (int)(Np / kI8BN), nty = (int)(Mp / kI8BM);
+        const int64_t nt = Kp / kI8BK;
+        int nz = i8_split((int64_t)ntx * nty, nt, m, n);
+        int64_t kt_per = (nt + nz - 1) / nz;
+        nz = (int)((nt + kt_per - 1) / kt_per);  // every part non-empty
+        int32_t *part = nz > 1 ? (int32_t *)ws.take((size_t)nz * (size_t)m * (size_t)n * 4) : nullptr;
+        if (!part) nz = 1;
         {
             ProfScope prof(FFP_PATH_INT8, 2.0 * (double)m * (double)n * (double)kc, s,
                            4.0 * ((double)m * (double)kc + (double)kc * (double)n +
                                   (be != 0.0 ? 2.0 : 1.0) * (double)m * (double)n));
-            const int ntx = (int)(Np / kI8BN), nty = (int)(Mp / kI8BM);
-            hipLaunchKernelGGL((k_fgemm_i8<L>), dim3((unsigned)(ntx * nty)), dim3(kI8Threads), 0, s, Ad, Bd, Kp,
+            hipLaunchKernelGGL((k_fgemm_i8<L>), dim3((unsigned)(ntx * nty * nz)), dim3(kI8Threads), 0, s, Ad, Bd, Kp,
                                planeA, planeB, m, n, C, ldc, F.pd, F.pinv, (double)alpha, be, wts[0], wts[1],
-                               wts[2], wts[3], ntx, nty);
+                               wts[2], wts[3], ntx, nty, kt_per, part);
+            if (part)
+                hipLaunchKernelGGL(k_i8_combine, dim3((unsigned)((m * n + 255) / 256)), dim3(256), 0, s, m, n, nz,
+                                   part, C, ldc, F.pd, F.pinv, (double)alpha, be);
         }
         FFP_HIP_CHECK(hipGetLastError());
         ws.release(mk);

@@ -67,6 +67,27 @@ def test_fgemm_parity(lib, orc, p):
                     assert np.array_equal(got, want), (p, path, m, n, k, ta, tb, alpha, beta)
 
 
+@pytest.mark.parametrize("p", [251, 65521, 131071, 8388593])
+def test_fgemm_int8_split_k(lib, orc, p):
+    """INT8 products with few output blocks and a long K run as several K
+    parts per block plus a combining pass: 4 equal parts, 4 uneven parts
+    (18 K tiles as 5 + 5 + 5 + 3) and 2 parts, with alpha, beta and
+    transposed operands."""
+    from paper_1402_3501_amd import PATH_INT8
+    rng = np.random.default_rng(p + 3)
+    for (m, n, k) in [(150, 260, 2000), (33, 17, 1100), (129, 128, 600)]:
+        for ta, tb in [(0, 0), (1, 1)]:
+            A = rng.integers(0, p, (k, m) if ta else (m, k)).astype(np.int32)
+            B = rng.integers(0, p, (n, k) if tb else (k, n)).astype(np.int32)
+            C = rng.integers(0, p, (m, n)).astype(np.int32)
+            for alpha, beta in [(1, 0), (int(rng.integers(0, p)), int(rng.integers(0, p)))]:
+                note("fgemm split-k", p, m, n, k, ta, tb, alpha, beta)
+                want = orc.fgemm(A, B, C, p, alpha, beta, bool(ta), bool(tb))
+                Cd = dev(C)
+                lib.fgemm(dev(A), dev(B), Cd, p, alpha, beta, bool(ta), bool(tb), path=PATH_INT8)
+                assert np.array_equal(host(Cd), want), (p, m, n, k, ta, tb, alpha, beta)
+
+
 def test_fgemm_long_k_reductions(lib, orc):
     """k far beyond the exactness bound: p = 8388593 needs a reduction every
     ~512 products, p = 94906249 one every 4."""
