@@ -521,6 +521,7 @@ struct Ctx {
     int64_t *rank_dev;   // device address of a pinned host word the leaves write their rank to
     int64_t *rank_host;  // the same word for the host
     int *flag_dev;       // device word: generic-attempt flag, zero-block flag
+    int64_t gen_k = 0;   // order of the running generic attempt
 };
 
 int read_rank(const Ctx &c, int64_t *out) {
@@ -813,6 +814,10 @@ int node_updates_gen(Ctx &c, int64_t m, int64_t n, int64_t h, int32_t *A, int64_
     return fgemm_sub(c, m - h, n - h, h, A + h * lda, lda, A + h, lda, A + h * lda + h, lda);
 }
 
+// returned (never to callers of the library) when a checkpoint of the
+// generic attempt finds a zero pivot: the rest of the attempt was not enqueued
+constexpr int kGenAbort = -1000;
+
 // Li / Ui: block-inverse slots from this block's diagonal offset on
 int lu_generic(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int *gflag, double *Li, double *Ui,
                int64_t d0) {
@@ -831,6 +836,15 @@ int lu_generic(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int *gflag
                              Li + kBlk, Ui + kBlk, c.s, A + 64 * lda, A + 64, nullptr, 0, nullptr, 0, d0 + 64);
     }
     FFP_CHECK(lu_generic(c, h, h, A, lda, gflag, Li, Ui, d0));
+    // checkpoints on the leading corner, once the leading block of order
+    // 1024..2047 and then of order 4096..8191 is factored, where at least
+    // three quarters of the attempt remain: one read-back each, and an input
+    // that is not generic that far skips the rest
+    if (d0 == 0 && c.gen_k >= 4 * h && ((h >= 1024 && h < 2048) || (h >= 4096 && h < 8192))) {
+        int64_t f = 0;
+        FFP_CHECK(read_flag(c, &f));
+        if (f != 0) return kGenAbort;
+    }
     FFP_CHECK(node_updates_gen(c, m, n, h, A, lda, Li, Ui));
     const int64_t off = (h / 64) * kBlk;  // h is a multiple of 64 whenever the rest is non-empty
     return lu_generic(c, m - h, n - h, A + h * lda + h, lda, gflag, Li + off, Ui + off, d0 + h);
@@ -880,7 +894,11 @@ int try_generic(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, bool *ok,
     FFP_CHECK(copy2d(m, n, A, lda, backup, n, s));
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c.flag_dev, 0);
     FFP_HIP_CHECK(hipGetLastError());
-    FFP_CHECK(lu_generic(c, m, n, A, lda, c.flag_dev, Li, Ui, 0));
+    {
+        c.gen_k = m < n ? m : n;
+        const int rc = lu_generic(c, m, n, A, lda, c.flag_dev, Li, Ui, 0);
+        if (rc != FFP_OK && rc != kGenAbort) return rc;
+    }
     int64_t flag = 0;
     FFP_CHECK(read_flag(c, &flag));
     *ok = flag == 0;

@@ -315,3 +315,8 @@ def test_pluq_generic_prefix_shortcuts(lib, orc):
     for tag, A in cases:
         for path in paths_for(p):
             _pluq_compare(lib, orc, A, p, path, tag)
+    # 4096 x 4096 with its first vanishing minor at order 300: the generic
+    # attempt stops at its checkpoint after the leading 1024 block
+    B = rng.integers(0, p, (4096, 4096)).astype(np.int32)
+    B[:300, :300] = wl.lowrank(300, 300, 299, p, 705)
+    _pluq_compare(lib, orc, B, p, 0, "planted minor 300, 4096")
