@@ -147,7 +147,13 @@ int ffp_flaswp(int dim, int64_t m, int64_t n, int32_t *A, int64_t lda, const int
  * A first attempt assumes a generic rank profile (all leading minors
  * nonzero: plain block LU, no rank read-backs) on a copy kept in the
  * workspace; a zero pivot restores A and runs the general recursion.  The
- * output is the same either way.
+ * attempt reads its flag back once at the end and, on large inputs, at up to
+ * two checkpoints on the way (after the leading blocks of order about 1024
+ * and 4096), stopping early when a zero pivot was met.  The index of the
+ * first zero pivot (every leading minor below it is nonzero) lets the
+ * general recursion factor leading tiles within that order as plain LU, and
+ * sub-blocks found zero (one reduction and read-back) skip their recursion.
+ * The output is the same either way.
  * -------------------------------------------------------------------------- */
 size_t ffp_pluq_workspace(int64_t m, int64_t n, uint32_t p, int path);
 int ffp_pluq(int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
