@@ -241,13 +241,14 @@ __global__ __launch_bounds__(kI8Threads) void k_fgemm_i8(const int8_t *__restric
 }
 
 // C <- alpha * (sum of the nz partial results) + beta * C, all mod p (each
-// partial is canonical, the sum of at most kI8MaxSplit of them is exact)
+// partial is canonical, the sum of at most kI8MaxSplit of them is exact);
+// row gi = blockIdx.y (split products have at most 128 blocks of 128 rows)
 __global__ __launch_bounds__(256) void k_i8_combine(int64_t m, int64_t n, int nz, const int32_t *__restrict__ part,
                                                     int32_t *__restrict__ C, int64_t ldc, double p, double pinv,
                                                     double alpha, double beta) {
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= m * n) return;
-    const int64_t gi = idx / n, gj = idx % n;
+    const int64_t gi = blockIdx.y, gj = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gj >= n) return;
+    const int64_t idx = gi * n + gj;
     double t = 0.0;
     for (int zz = 0; zz < nz; ++zz) t += (double)part[(int64_t)zz * m * n + idx];
     double rres = mod_canon(t, p, pinv);
@@ -279,6 +280,7 @@ size_t fgemm_i8_ws(const Field &F, int64_t m, int64_t n, int64_t k) {
 // tiles, the partial results within kI8SplitBytes
 static int i8_split(int64_t tiles, int64_t nt, int64_t m, int64_t n) {
     int z = 1;
+    if (m > 65535) return 1;  // the combining pass runs one grid row per output row
     while (z < kI8MaxSplit && tiles * z * 2 <= 256 && nt / (z * 2) >= 4 && (int64_t)(z * 2) * m * n * 4 <= kI8SplitBytes)
         z *= 2;
     return z;
@@ -330,8 +332,8 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
                                planeA, planeB, m, n, C, ldc, F.pd, F.pinv, (double)alpha, be, wts[0], wts[1],
                                wts[2], wts[3], ntx, nty, kt_per, part);
             if (part)
-                hipLaunchKernelGGL(k_i8_combine, dim3((unsigned)((m * n + 255) / 256)), dim3(256), 0, s, m, n, nz,
-                                   part, C, ldc, F.pd, F.pinv, (double)alpha, be);
+                hipLaunchKernelGGL(k_i8_combine, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0, s, m, n,
+                                   nz, part, C, ldc, F.pd, F.pinv, (double)alpha, be);
         }
         FFP_HIP_CHECK(hipGetLastError());
         ws.release(mk);
