@@ -102,7 +102,7 @@ size_t ffp_fgemm_workspace(int transA, int transB, int64_t m, int64_t n, int64_t
     const int eff = resolve_path(path, p, m, n, k);
     if (eff != FFP_PATH_INT8 || int8_limbs(p) == 0) return 0;
     Field F(p);
-    return fgemm_i8_ws(F, m, n, k) + 256;
+    return fgemm_i8_ws(F, m, n, k) + fgemm_i8_split_ws(m, n) + 256;
 }
 
 int ffp_fgemm(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t p, uint32_t alpha,

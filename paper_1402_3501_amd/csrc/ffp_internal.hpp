@@ -74,6 +74,8 @@ int fgemm_f64(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, u
 
 // same result through signed 8-bit limbs on INT8 matrix cores (workspace from the arena)
 size_t fgemm_i8_ws(const Field &F, int64_t m, int64_t n, int64_t k);
+// optional workspace of the split-K partial results (see fgemm_i8.hip)
+size_t fgemm_i8_split_ws(int64_t m, int64_t n);
 int fgemm_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
              const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta,
              int32_t *C, int64_t ldc, Arena &ws, hipStream_t s);

@@ -269,10 +269,16 @@ size_t fgemm_i8_ws(const Field &F, int64_t m, int64_t n, int64_t k) {
     const int L = F.limbs > 0 ? F.limbs : 3;
     const int64_t kc = k < kchunk_for(L) ? k : kchunk_for(L);
     const int64_t Kp = rup(kc > 0 ? kc : 1, kI8BK);
-    const int64_t Mp = rup(m, kI8BM), Np = rup(n, kI8BN);
-    const int64_t split = (int64_t)kI8MaxSplit * Mp * Np * 4 < kI8SplitBytes ? (int64_t)kI8MaxSplit * Mp * Np * 4
-                                                                            : kI8SplitBytes;
-    return (size_t)L * (size_t)(Mp + Np) * (size_t)Kp + (size_t)split + 1280;
+    return (size_t)L * (size_t)(rup(m, kI8BM) + rup(n, kI8BN)) * (size_t)Kp + 1024;
+}
+
+// The split-K partial results are optional workspace: a product splits K
+// only when the arena still has room for them after the limb planes (the
+// workspace sizes of the factorisations leave it), otherwise it runs
+// unsplit.  A caller that wants the split for a lone product adds this.
+size_t fgemm_i8_split_ws(int64_t m, int64_t n) {
+    const int64_t b = (int64_t)kI8MaxSplit * rup(m, kI8BM) * rup(n, kI8BN) * 4;
+    return (size_t)(b < kI8SplitBytes ? b : kI8SplitBytes) + 256;
 }
 
 // K parts for a product of `tiles` output blocks and nt K tiles: enough to
@@ -322,8 +328,16 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
         int nz = i8_split((int64_t)ntx * nty, nt, m, n);
         int64_t kt_per = (nt + nz - 1) / nz;
         nz = (int)((nt + kt_per - 1) / kt_per);  // every part non-empty
-        int32_t *part = nz > 1 ? (int32_t *)ws.take((size_t)nz * (size_t)m * (size_t)n * 4) : nullptr;
-        if (!part) nz = 1;
+        // optional: without room for the partial results the product runs unsplit
+        int32_t *part = nullptr;
+        if (nz > 1) {
+            const size_t bytes = (size_t)nz * (size_t)m * (size_t)n * 4;
+            if (ws.used + bytes + 256 <= ws.cap) part = (int32_t *)ws.take(bytes);
+        }
+        if (!part) {
+            nz = 1;
+            kt_per = nt;
+        }
         {
             ProfScope prof(FFP_PATH_INT8, 2.0 * (double)m * (double)n * (double)kc, s,
                            4.0 * ((double)m * (double)kc + (double)kc * (double)n +

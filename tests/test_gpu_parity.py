@@ -217,6 +217,17 @@ def test_pluq_random_shapes(lib, orc, p):
                 _pluq_compare(lib, orc, A, p, path, "uniform")
 
 
+@pytest.mark.parametrize("p", [251, 65521, 131071])
+def test_pluq_auto_rank_deficient(lib, orc, p):
+    """The AUTO path on rank-deficient inputs of moderate size: the general
+    recursion with its second stream, the generic-prefix and zero-block
+    shortcuts, and workspace sized by the AUTO rule."""
+    rng = np.random.default_rng(p + 11)
+    for (m, n, r) in [(300, 260, 170), (257, 300, 100), (700, 300, 250), (1000, 900, 600), (130, 1100, 90)]:
+        A = wl.lowrank(m, n, r, p, int(rng.integers(1 << 40)))
+        _pluq_compare(lib, orc, A, p, 0, f"auto lowrank r={r}")
+
+
 def test_pluq_special_matrices(lib, orc):
     p = 131071
     rng = np.random.default_rng(17)
