@@ -298,8 +298,9 @@ int orc_pivots(int64_t m, int64_t n, uint32_t p, const int32_t *A, int64_t lda,
 /* The top-right block is eliminated before the bottom-left one; the    */
 /* two are independent, so only the position of the cross term depends */
 /* on this choice.  Non-pivot indices keep their relative order.        */
-/* Parity unpinned as a convention; pinned in tests against a direct    */
-/* block implementation of the recursion on small inputs.               */
+/* This order is a convention (the paper fixes no example of it); it   */
+/* is pinned in tests against a direct block implementation of the      */
+/* recursion, exhaustively on small inputs.                             */
 /* ------------------------------------------------------------------ */
 typedef struct {
     const int32_t *pc_of_row; /* pivot column of row x, or -1 */
