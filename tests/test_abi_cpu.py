@@ -108,6 +108,31 @@ def test_workspace_queries(lib):
     assert lib.ffp_pluq_workspace(0, 0, 7, 1) > 0
 
 
+def test_auto_path_crossover(lib):
+    """AUTO takes INT8 products from 0.8e9 field operations (several limbs) and,
+    with one limb, from k >= 128 and 256 x 256 outputs."""
+    assert lib.ffp_auto_path(131071, 768, 768, 768) == 2       # 0.91e9
+    assert lib.ffp_auto_path(131071, 512, 512, 512) == 1       # 0.27e9
+    assert lib.ffp_auto_path(131071, 1024, 1024, 256) == 1     # 0.54e9
+    assert lib.ffp_auto_path(251, 256, 256, 128) == 2
+    assert lib.ffp_auto_path(251, 256, 256, 127) == 1
+    assert lib.ffp_auto_path(94906249, 8192, 8192, 8192) == 1  # beyond the INT8 limbs
+
+
+def test_workspace_covers_split_k(lib):
+    """A lone INT8 product's workspace holds the limb planes and room for the
+    split-K partial results (at most 4 parts of m x n int32, at most 32 MiB);
+    the AUTO PLUQ workspace is at least the FP64 one."""
+    m, n, k = 300, 260, 2000                 # 3 x 3 output blocks, 32 K tiles
+    planes = 3 * (384 + 384) * 2048          # 3 limbs, padded rows x padded K
+    split = 4 * 384 * 384 * 4
+    assert lib.ffp_fgemm_workspace(0, 0, m, n, k, 131071, 2) >= planes + split
+    big = lib.ffp_fgemm_workspace(0, 0, 16384, 16384, 16384, 131071, 2)
+    assert big >= 3 * 2 * 16384 * 16384 and big < 3 * 2 * 16384 * 16384 + (33 << 20)
+    for (mm, nn) in [(300, 260), (2048, 2048), (8192, 8192)]:
+        assert lib.ffp_pluq_workspace(mm, nn, 131071, 0) >= lib.ffp_pluq_workspace(mm, nn, 131071, 1)
+
+
 def test_perm_swaps_roundtrip(lib):
     rng = np.random.default_rng(0)
     for n in (0, 1, 2, 5, 17, 100):
