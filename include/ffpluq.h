@@ -81,7 +81,11 @@ int ffp_auto_path(uint32_t p, int64_t m, int64_t n, int64_t k);
  *   m x k, or k x m when transposed), op(B) is k x n, C is m x n.
  *   alpha, beta: residues in [0, p).  beta = 0 means C is not read.
  *   path: ffp_path.  FP64 requires p <= FFP_P_MAX_FP64, INT8 p <= FFP_P_MAX_INT8.
- * The INT8 path splits A and B into limbs in the workspace.
+ * The INT8 path splits A and B into limbs in the workspace; when the grid
+ * of 128 x 128 output blocks is too small to fill the device it also splits
+ * the inner dimension over up to 4 workgroups per block, with their partial
+ * results (at most 4 m n int32, capped at 32 MiB) in the workspace and one
+ * more launch to combine them.  The workspace query includes that room.
  * -------------------------------------------------------------------------- */
 size_t ffp_fgemm_workspace(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t p,
                            int path);
