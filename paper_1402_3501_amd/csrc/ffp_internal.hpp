@@ -72,6 +72,13 @@ int fgemm_f64(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, u
               const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta,
               int32_t *C, int64_t ldc, hipStream_t s);
 
+// two products C_i <- alpha A_i B_i + beta C_i (no transposes, the same k) in
+// one launch when both are small-product shapes, else one after the other
+int fgemm_f64_pair(const Field &F, int64_t m0, int64_t n0, const int32_t *A0, int64_t lda0, const int32_t *B0,
+                   int64_t ldb0, int32_t *C0, int64_t ldc0, int64_t m1, int64_t n1, const int32_t *A1, int64_t lda1,
+                   const int32_t *B1, int64_t ldb1, int32_t *C1, int64_t ldc1, int64_t k, uint32_t alpha,
+                   uint32_t beta, hipStream_t s);
+
 // same result through signed 8-bit limbs on INT8 matrix cores (workspace from the arena)
 size_t fgemm_i8_ws(const Field &F, int64_t m, int64_t n, int64_t k);
 // optional workspace of the split-K partial results (see fgemm_i8.hip)

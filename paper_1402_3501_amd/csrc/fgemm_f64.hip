@@ -313,16 +313,14 @@ __global__ __launch_bounds__(256) void k_fgemm_f64_k64(int64_t m, int64_t n, int
 // tiles, each reduced to |x| <= p/2, are summed through LDS; for alpha = +-1
 // and beta in {0, 1} the epilogue is one reduction of +-acc + C.
 template <bool TA, bool TB, bool RED>
-__global__ __launch_bounds__(256) void k_fgemm_f64_sk(int m, int n, int k, const int32_t *__restrict__ A,
-                                                      uint32_t lda, const int32_t *__restrict__ B, uint32_t ldb,
-                                                      int32_t *__restrict__ C, uint32_t ldc, double p, double pinv,
-                                                      int32_t half, double alpha, double beta, int kchunk_steps,
-                                                      int vecA, int vecB) {
+__device__ __forceinline__ void sk_body(int m0, int n0, int m, int n, int k, const int32_t *__restrict__ A,
+                                        uint32_t lda, const int32_t *__restrict__ B, uint32_t ldb,
+                                        int32_t *__restrict__ C, uint32_t ldc, double p, double pinv, int32_t half,
+                                        double alpha, double beta, int kchunk_steps, int vecA, int vecB) {
     constexpr int T = 32, KD = 32, NWV = 4;
     __shared__ double part[NWV][T][T + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, kq = lane >> 4;
-    const int m0 = blockIdx.y * T, n0 = blockIdx.x * T;
     const int32_t ip = (int32_t)p;
     const int nst = (k + KD - 1) / KD;
     // one operand's 2 x 8 entries of a stage: rows (or columns) 16 u + r16
@@ -441,6 +439,41 @@ __global__ __launch_bounds__(256) void k_fgemm_f64_sk(int m, int n, int k, const
     }
 }
 
+template <bool TA, bool TB, bool RED>
+__global__ __launch_bounds__(256) void k_fgemm_f64_sk(int m, int n, int k, const int32_t *__restrict__ A,
+                                                      uint32_t lda, const int32_t *__restrict__ B, uint32_t ldb,
+                                                      int32_t *__restrict__ C, uint32_t ldc, double p, double pinv,
+                                                      int32_t half, double alpha, double beta, int kchunk_steps,
+                                                      int vecA, int vecB) {
+    sk_body<TA, TB, RED>((int)blockIdx.y * 32, (int)blockIdx.x * 32, m, n, k, A, lda, B, ldb, C, ldc, p, pinv, half,
+                         alpha, beta, kchunk_steps, vecA, vecB);
+}
+
+// Two independent small products with the same k, alpha and beta (the two
+// updates between the levels of a pair of panel solves) in one launch: the
+// first o0.nblk workgroups take the first product's 32 x 32 tiles, the rest
+// the second's.
+struct SkOp {
+    int m, n;
+    const int32_t *A;
+    uint32_t lda;
+    const int32_t *B;
+    uint32_t ldb;
+    int32_t *C;
+    uint32_t ldc;
+    int vecA, vecB, ntx, nblk;
+};
+template <bool RED>
+__global__ __launch_bounds__(256) void k_fgemm_f64_sk_pair(SkOp o0, SkOp o1, int k, double p, double pinv,
+                                                           int32_t half, double alpha, double beta,
+                                                           int kchunk_steps) {
+    const bool second = (int)blockIdx.x >= o0.nblk;
+    const SkOp o = second ? o1 : o0;
+    const int b = second ? (int)blockIdx.x - o0.nblk : (int)blockIdx.x;
+    sk_body<false, false, RED>((b / o.ntx) * 32, (b % o.ntx) * 32, o.m, o.n, k, o.A, o.lda, o.B, o.ldb, o.C, o.ldc,
+                               p, pinv, half, alpha, beta, kchunk_steps, o.vecA, o.vecB);
+}
+
 template <int BM, int BN, bool RED>
 static void launch_tiles(int ta, int tb, dim3 grid, hipStream_t s, int64_t m, int64_t n, int64_t k,
                          const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, int32_t *C,
@@ -458,6 +491,57 @@ static void launch_tiles(int ta, int tb, dim3 grid, hipStream_t s, int64_t m, in
 #undef FFP_LAUNCH
 }
 
+// the small-product kernel takes a product with fewer than 192 tiles of
+// 128 and (fewer than 256 tiles of 64 or k <= 256), with 32-bit indices
+static bool takes_sk(int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb, int64_t ldc) {
+    const int64_t big_tiles = ((m + 127) / 128) * ((n + 127) / 128);
+    return big_tiles < 192 && (((m + 63) / 64) * ((n + 63) / 64) < 256 || k <= 256) && m < (1ll << 30) &&
+           n < (1ll << 30) && k < (1ll << 30) && lda < (1ll << 31) && ldb < (1ll << 31) && ldc < (1ll << 31);
+}
+
+int fgemm_f64_pair(const Field &F, int64_t m0, int64_t n0, const int32_t *A0, int64_t lda0, const int32_t *B0,
+                   int64_t ldb0, int32_t *C0, int64_t ldc0, int64_t m1, int64_t n1, const int32_t *A1, int64_t lda1,
+                   const int32_t *B1, int64_t ldb1, int32_t *C1, int64_t ldc1, int64_t k, uint32_t alpha,
+                   uint32_t beta, hipStream_t s) {
+    if (m0 <= 0 || n0 <= 0 || m1 <= 0 || n1 <= 0 || k <= 0 || !takes_sk(m0, n0, k, lda0, ldb0, ldc0) ||
+        !takes_sk(m1, n1, k, lda1, ldb1, ldc1)) {
+        FFP_CHECK(fgemm_f64(F, 0, 0, m0, n0, k, alpha, A0, lda0, B0, ldb0, beta, C0, ldc0, s));
+        return fgemm_f64(F, 0, 0, m1, n1, k, alpha, A1, lda1, B1, ldb1, beta, C1, ldc1, s);
+    }
+    const bool red = k > F.kexact;
+    const int ksteps = (int)(F.kexact / 4 > (1 << 30) ? (1 << 30) : (F.kexact / 4 < 1 ? 1 : F.kexact / 4));
+    auto op = [](int64_t m, int64_t n, const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, int32_t *C,
+                 int64_t ldc) {
+        SkOp o;
+        o.m = (int)m;
+        o.n = (int)n;
+        o.A = A;
+        o.lda = (uint32_t)lda;
+        o.B = B;
+        o.ldb = (uint32_t)ldb;
+        o.C = C;
+        o.ldc = (uint32_t)ldc;
+        o.vecA = ((((uintptr_t)A) | (uintptr_t)(lda * 4)) & 15) == 0;
+        o.vecB = ((((uintptr_t)B) | (uintptr_t)(ldb * 4)) & 15) == 0;
+        o.ntx = (int)((n + 31) / 32);
+        o.nblk = o.ntx * (int)((m + 31) / 32);
+        return o;
+    };
+    const SkOp o0 = op(m0, n0, A0, lda0, B0, ldb0, C0, ldc0), o1 = op(m1, n1, A1, lda1, B1, ldb1, C1, ldc1);
+    const double mn = (double)m0 * (double)n0 + (double)m1 * (double)n1;
+    ProfScope prof(FFP_PATH_FP64, 2.0 * mn * (double)k, s,
+                   4.0 * ((double)(m0 + m1) * (double)k + (double)k * (double)(n0 + n1) + (beta != 0 ? 2.0 : 1.0) * mn));
+    const dim3 grid((unsigned)(o0.nblk + o1.nblk));
+    if (red)
+        hipLaunchKernelGGL((k_fgemm_f64_sk_pair<true>), grid, dim3(256), 0, s, o0, o1, (int)k, F.pd, F.pinv,
+                           (int32_t)F.half, (double)alpha, (double)beta, ksteps);
+    else
+        hipLaunchKernelGGL((k_fgemm_f64_sk_pair<false>), grid, dim3(256), 0, s, o0, o1, (int)k, F.pd, F.pinv,
+                           (int32_t)F.half, (double)alpha, (double)beta, ksteps);
+    FFP_HIP_CHECK(hipGetLastError());
+    return FFP_OK;
+}
+
 int fgemm_f64(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
               const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta,
               int32_t *C, int64_t ldc, hipStream_t s) {
@@ -473,8 +557,7 @@ int fgemm_f64(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, u
         dim3 grid((unsigned)((n + 127) / 128), (unsigned)((m + 127) / 128));
         if (red) launch_tiles<128, 128, true>(ta, tb, grid, s, m, n, k, A, lda, B, ldb, C, ldc, p, pinv, half, a, b, ksteps);
         else launch_tiles<128, 128, false>(ta, tb, grid, s, m, n, k, A, lda, B, ldb, C, ldc, p, pinv, half, a, b, ksteps);
-    } else if ((((m + 63) / 64) * ((n + 63) / 64) < 256 || k <= 256) && m < (1ll << 30) && n < (1ll << 30) && k < (1ll << 30) &&
-               lda < (1ll << 31) && ldb < (1ll << 31) && ldc < (1ll << 31)) {
+    } else if (takes_sk(m, n, k, lda, ldb, ldc)) {
         dim3 grid((unsigned)((n + 31) / 32), (unsigned)((m + 31) / 32));
         // 16-byte loads along K need 16-byte aligned rows
         const int vA = ((((uintptr_t)A) | (uintptr_t)(lda * 4)) & 15) == 0;

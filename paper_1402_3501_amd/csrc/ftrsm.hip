@@ -609,11 +609,22 @@ int ftrsm_pair_gen(int path, const Field &F, int64_t h, const int32_t *T, int64_
     const int64_t d1 = ((h / 2 + kTBB - 1) / kTBB) * kTBB < h ? ((h / 2 + kTBB - 1) / kTBB) * kTBB : kTBB;
     const int64_t d2 = h - d1, off = (d1 / kTB) * kTB * kTB;
     FFP_CHECK(ftrsm_pair_gen(path, F, d1, T, ldt, nvd, Bd, nve, Be, ldb, Li, Ui, ws, s));
-    // D2 -= L21 D1 (rows d1.. of the left panel), E2 -= E1 U12 (columns d1.. of the right one)
-    if (nvd > 0)
-        FFP_CHECK(fgemm_any(path, F, 0, 0, d2, nvd, d1, minus1, T + d1 * ldt, ldt, Bd, ldb, 1, Bd + d1 * ldb, ldb, ws, s));
-    if (nve > 0)
-        FFP_CHECK(fgemm_any(path, F, 0, 0, nve, d2, d1, minus1, Be, ldb, T + d1, ldt, 1, Be + d1, ldb, ws, s));
+    // D2 -= L21 D1 (rows d1.. of the left panel), E2 -= E1 U12 (columns d1.. of the right one);
+    // both on the FP64 path: one launch
+    auto on_fp64 = [&](int64_t mm, int64_t nn) {
+        const int eff = path == FFP_PATH_AUTO ? resolve_path(path, F.p, mm, nn, d1) : path;
+        return !(eff == FFP_PATH_INT8 && F.limbs > 0);
+    };
+    if (!ws.counting && nvd > 0 && nve > 0 && on_fp64(d2, nvd) && on_fp64(nve, d2)) {
+        FFP_CHECK(fgemm_f64_pair(F, d2, nvd, T + d1 * ldt, ldt, Bd, ldb, Bd + d1 * ldb, ldb, nve, d2, Be, ldb, T + d1,
+                                 ldt, Be + d1, ldb, d1, minus1, 1, s));
+    } else {
+        if (nvd > 0)
+            FFP_CHECK(fgemm_any(path, F, 0, 0, d2, nvd, d1, minus1, T + d1 * ldt, ldt, Bd, ldb, 1, Bd + d1 * ldb, ldb,
+                                ws, s));
+        if (nve > 0)
+            FFP_CHECK(fgemm_any(path, F, 0, 0, nve, d2, d1, minus1, Be, ldb, T + d1, ldt, 1, Be + d1, ldb, ws, s));
+    }
     return ftrsm_pair_gen(path, F, d2, T + d1 * ldt + d1, ldt, nvd, Bd + d1 * ldb, nve, Be + d1, ldb, Li + off,
                           Ui + off, ws, s);
 }
