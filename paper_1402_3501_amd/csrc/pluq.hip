@@ -450,7 +450,6 @@ static int iota(int32_t *v, int64_t n, hipStream_t s) {
 // ===================================================================== host recursion
 namespace {
 std::mutex g_pin_mu;
-int64_t *g_pin = nullptr;  // pinned host word for the flag read-back
 // Host words the leaves of the general recursion write their rank into
 // directly (pinned, coherent, device-visible): the host reads a rank after
 // one stream synchronisation, with no copy on the stream.  One word per
