@@ -147,3 +147,16 @@ def test_perm_swaps_roundtrip(lib):
         assert np.array_equal(ffp.swaps_to_perm(ipiv), perm)
     with pytest.raises(ffp.FFPError):
         ffp.perm_to_swaps(np.array([0, 0, 1], np.int32))
+
+
+def test_bench_refuses_several_gpus():
+    """The benchmark measures one GPU: asked for more it exits with a message
+    before touching any device."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
