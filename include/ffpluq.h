@@ -45,7 +45,7 @@ typedef void *ffp_stream_t; /* hipStream_t */
 #define FFP_E_P_RANGE (-102)     /* p too large for the requested path */
 #define FFP_E_WORKSPACE (-103)   /* workspace missing or too small */
 #define FFP_E_HIP (-104)         /* a HIP runtime call failed */
-#define FFP_E_RANGE (-105)       /* an input entry lies outside [0, p) (validating calls only) */
+#define FFP_E_RANGE (-105)       /* an input entry lies outside [0, p) (ffp_check_range only) */
 #define FFP_E_UNSUPPORTED (-106) /* valid request this build does not implement */
 #define FFP_E_NODEVICE (-107)    /* no gfx950 device / kernels failed to load */
 #define FFP_E_INTERNAL (-108)    /* internal consistency check failed; A is restored */
@@ -142,7 +142,9 @@ int ffp_flaswp(int dim, int64_t m, int64_t n, int32_t *A, int64_t lda, const int
  *   rrp / crp: device int32 arrays of min(m, n) entries receiving the sorted
  *     row / column rank profile in their first r entries (may be NULL).
  * The host drives the recursion and reads each sub-block's rank back, so
- * the call synchronises with `stream` internally.  Within a node of the
+ * the call synchronises with `stream` internally and cannot be captured in
+ * a graph; ffp_lu_nopiv (generic rank profile) and ffp_pluq_batched are the
+ * asynchronous, capturable alternatives.  Within a node of the
  * general recursion the solve E = C1 U1^-1 and its product run on a second
  * stream that the library owns (one per device, default priority, shared by
  * all calls on the device), ordered against `stream` with events and joined
@@ -165,6 +167,32 @@ int ffp_pluq(int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int32_t 
              size_t ws_bytes, ffp_stream_t stream);
 
 /* --------------------------------------------------------------------------
+ * lu_nopiv -- the PLUQ of Section 2.1 (getrf) for an input of generic rank
+ * profile (every leading principal minor nonzero, the assumption Section 3
+ * makes for its reduction counts): then R_A is the leading diagonal, P and Q
+ * are the identity and A = L U without pivoting, so no rank ever has to be
+ * read back.  Fully asynchronous on `stream` (no host synchronisation, no
+ * allocation: graph-capturable), unlike ffp_pluq.
+ *   info_dev: device int32 receiving 0 when every pivot was nonzero (A then
+ *     holds L\U exactly as ffp_pluq returns it, rank min(m, n), P = Q = id),
+ *     otherwise 1 + the diagonal index of the first zero pivot (A is then
+ *     left in an unspecified state: keep a copy to fall back on ffp_pluq).
+ * Workspace: ffp_lu_nopiv_workspace bytes.
+ * -------------------------------------------------------------------------- */
+size_t ffp_lu_nopiv_workspace(int64_t m, int64_t n, uint32_t p, int path);
+int ffp_lu_nopiv(int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int32_t *info_dev, int path,
+                 void *ws, size_t ws_bytes, ffp_stream_t stream);
+
+/* --------------------------------------------------------------------------
+ * check_range -- the validating call: FFP_E_RANGE if some entry of the m x n
+ * matrix A (device, leading dimension lda) lies outside [0, p), else FFP_OK.
+ * The other entry points take canonical residues without checking them
+ * (an entry >= p gives unspecified bits); callers that cannot vouch for
+ * their input run this first.  Synchronises `stream` (one read-back).
+ * -------------------------------------------------------------------------- */
+int ffp_check_range(int64_t m, int64_t n, uint32_t p, const int32_t *A, int64_t lda, ffp_stream_t stream);
+
+/* --------------------------------------------------------------------------
  * pluq_batched -- the same factorisation for `batch` independent matrices of
  * uneven shapes (the heterogeneous pivot blocks of Section 4.1), in one
  * persistent kernel launch with no host synchronisation (graph-capturable).
@@ -174,7 +202,9 @@ int ffp_pluq(int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int32_t 
  *     offsets of each P (m_i entries) / Q (n_i entries) in P_packed / Q_packed;
  *   rank_arr: device int32[batch]; rrp_packed / crp_packed use P_off / Q_off
  *     and receive the sorted profiles in their first r_i entries (may be NULL).
- *   max_m, max_n: host upper bounds of the shapes (used to size the launch).
+ *   max_m, max_n: host upper bounds of the shapes (used to size the launch
+ *     and the workspace).  A matrix whose m_i or n_i lies outside [0, max_m]
+ *     or [0, max_n] is not touched and its rank_arr entry reads -1.
  * Every output equals what ffp_pluq returns for that matrix alone.
  * -------------------------------------------------------------------------- */
 #define FFP_BATCH_MAX_DIM 1024
@@ -208,27 +238,36 @@ int ffp_pluq_batched_tune(int32_t batch, const int32_t *m_arr, const int32_t *n_
                           float *ms_out, void *ws, size_t ws_bytes, ffp_stream_t stream);
 
 /* --------------------------------------------------------------------------
- * Host helpers (host pointers): conversion between an index vector and the
- * LAPACK laswp form (sequence of swaps: for i = 0..len-1, swap entries i and
- * ipiv[i]).  perm[i] = original index placed at position i.
+ * Host helpers (host pointers): Section 2.1 describes laswp as applying a
+ * sequence of swaps, while this library's permutations are index vectors
+ * (order-preserving rotations, see ffp_flaswp).  These convert between the
+ * two: ipiv is the LAPACK laswp form (for i = 0..len-1, swap entries i and
+ * ipiv[i]), perm[i] = original index placed at position i.  Return -2 when
+ * the input is not a permutation / not a valid swap sequence.
  * -------------------------------------------------------------------------- */
 int ffp_perm_to_swaps(int64_t len, const int32_t *perm, int32_t *ipiv);
 int ffp_swaps_to_perm(int64_t len, const int32_t *ipiv, int32_t *perm);
 
 /* --------------------------------------------------------------------------
  * Kernel timing (for benchmarks): when enabled, the library brackets each
- * launch of its dense product kernels with HIP events on the launching
- * stream and accumulates, per arithmetic path, the number of launches, the
- * summed event time and the summed algorithmic work (2*m*n*k field
- * operations).  Reading synchronises the recorded events.
+ * launch of its kernels with HIP events on the launching stream and
+ * accumulates, per kernel family ("kind", 1 .. FFP_PROFILE_KINDS - 1), the
+ * number of launches, the summed event time, the summed algorithmic work in
+ * field operations (2 m n k per product, d^2 nv per triangular solve of a
+ * d x d triangle with nv vectors, 2 m n k - (m + n) k^2 + 2 k^3 / 3 per
+ * elimination of rank k plus the products fused into a leaf) and the summed
+ * algorithmic bytes (operands read once, results written once).  Kind 1 is
+ * the FP64 product kernels and kind 2 the INT8 product kernel (FFP_PATH_FP64
+ * and FFP_PATH_INT8); ffp_profile_kind_name names every kind after its
+ * kernels.  Reading synchronises the recorded events.
  * -------------------------------------------------------------------------- */
+#define FFP_PROFILE_KINDS 11
 int ffp_profile_enable(int on);
 int ffp_profile_reset(void);
-int ffp_profile_read(int path, int64_t *launches, double *milliseconds, double *field_ops);
-/* the summed algorithmic memory traffic of the same launches: operands read
- * once and the result written once, (m k + k n + m n [+ m n if beta != 0]) * 4
- * bytes per product (the INT8 path counts its int32 operands, not the limbs) */
-int ffp_profile_read_bytes(int path, double *bytes);
+int ffp_profile_read(int kind, int64_t *launches, double *milliseconds, double *field_ops);
+int ffp_profile_read_bytes(int kind, double *bytes);
+/* name of the kernel family `kind` (static storage), NULL outside the range */
+const char *ffp_profile_kind_name(int kind);
 
 #ifdef __cplusplus
 }

@@ -58,6 +58,9 @@ def load():
         "ffp_flaswp": ([i32, i64, i64, vp, i64, vp, i32, vp, sz, vp], i32),
         "ffp_pluq_workspace": ([i64, i64, u32, i32], sz),
         "ffp_pluq": ([i64, i64, u32, vp, i64, vp, vp, vp, ctypes.POINTER(i64), vp, vp, i32, vp, sz, vp], i32),
+        "ffp_lu_nopiv_workspace": ([i64, i64, u32, i32], sz),
+        "ffp_lu_nopiv": ([i64, i64, u32, vp, i64, vp, i32, vp, sz, vp], i32),
+        "ffp_check_range": ([i64, i64, u32, vp, i64, vp], i32),
         "ffp_pluq_batched_workspace": ([i32, i32, i32, u32, i32], sz),
         "ffp_pluq_batched": ([i32, vp, vp, i32, i32, u32, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, sz, vp], i32),
         "ffp_pluq_batched_tune_workspace": ([i32, i32, i32, i64], sz),
@@ -70,6 +73,7 @@ def load():
         "ffp_profile_read": ([i32, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double)], i32),
         "ffp_profile_read_bytes": ([i32, ctypes.POINTER(ctypes.c_double)], i32),
+        "ffp_profile_kind_name": ([i32], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -236,6 +240,41 @@ def pluq_into(A, p: int, P, Q, rank_dev, rrp, crp, ws, path: int = PATH_AUTO) ->
     return int(r.value)
 
 
+def lu_nopiv(A, p: int, info=None, ws=None, path: int = PATH_AUTO):
+    """Plain LU in place for an input of generic rank profile (no host
+    synchronisation).  Returns the device int32 ``info``: 0 when every pivot
+    was nonzero, else 1 + the diagonal index of the first zero pivot."""
+    torch = _torch()
+    lib = load()
+    a, lda = _mat(A, "A")
+    m, n = A.shape
+    if info is None:
+        info = torch.empty(1, dtype=torch.int32, device=A.device)
+    need = lib.ffp_lu_nopiv_workspace(m, n, p, path)
+    if ws is None:
+        keep, wsp = _workspace(need, A.device)
+        wsz = need
+    else:
+        keep, wsp, wsz = ws, ctypes.c_void_p(ws.data_ptr()), ws.numel()
+    _check(lib.ffp_lu_nopiv(m, n, p, a, lda, _vec(info, "info"), path, wsp, wsz, _stream(A)), "ffp_lu_nopiv")
+    return info
+
+
+def lu_nopiv_workspace(m: int, n: int, p: int, path: int = PATH_AUTO) -> int:
+    return int(load().ffp_lu_nopiv_workspace(m, n, p, path))
+
+
+def check_range(A, p: int) -> bool:
+    """True when every entry of A lies in [0, p) (synchronises)."""
+    a, lda = _mat(A, "A")
+    m, n = A.shape
+    rc = load().ffp_check_range(m, n, p, a, lda, _stream(A))
+    if rc == -105:
+        return False
+    _check(rc, "ffp_check_range")
+    return True
+
+
 @dataclass
 class BatchedResult:
     P: object
@@ -370,6 +409,25 @@ def profile_read(path: int):
     _check(load().ffp_profile_read(path, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(ops)),
            "ffp_profile_read")
     return int(n.value), float(ms.value), float(ops.value)
+
+
+PROFILE_KINDS = 11
+
+
+def profile_kind_name(kind: int) -> str:
+    name = load().ffp_profile_kind_name(kind)
+    return name.decode() if name else ""
+
+
+def profile_read_all() -> dict:
+    """{kind name: (launches, milliseconds, field_ops, bytes)} of every kernel
+    family with at least one timed launch."""
+    out = {}
+    for kind in range(1, PROFILE_KINDS):
+        n, ms, ops = profile_read(kind)
+        if n:
+            out[profile_kind_name(kind)] = (n, ms, ops, profile_read_bytes(kind))
+    return out
 
 
 def profile_read_bytes(path: int) -> float:

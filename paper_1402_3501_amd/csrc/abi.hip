@@ -113,7 +113,7 @@ int ffp_fgemm(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t 
     if (m < 0) return -3;
     if (n < 0) return -4;
     if (k < 0) return -5;
-    FFP_CHECK(check_field(p, path, 6, 16));
+    FFP_CHECK(check_field(p, path, 6, 15));
     if (alpha >= p) return -7;
     if (beta >= p) return -12;
     if (m == 0 || n == 0) return FFP_OK;
@@ -252,6 +252,43 @@ int ffp_pluq(int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int32_t 
     return FFP_OK;
 }
 
+// ------------------------------------------------------------------ lu_nopiv
+size_t ffp_lu_nopiv_workspace(int64_t m, int64_t n, uint32_t p, int path) {
+    if (p < 2 || m < 0 || n < 0) return 0;
+    Field F(p);
+    const int eff = pluq_path(path, p, m, n);
+    return pluq_ws(m, n, F, eff == FFP_PATH_INT8 && int8_limbs(p) > 0 ? FFP_PATH_INT8 : FFP_PATH_FP64) + 4096;
+}
+
+int ffp_lu_nopiv(int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int32_t *info_dev, int path, void *ws,
+                 size_t ws_bytes, ffp_stream_t stream) {
+    if (m < 0 || m > INT32_MAX) return -1;
+    if (n < 0 || n > INT32_MAX) return -2;
+    FFP_CHECK(check_field(p, path, 3, 7));
+    if (m > 0 && n > 0 && !A) return -4;
+    if (lda < (n > 1 ? n : 1)) return -5;
+    if (!info_dev) return -6;
+    const size_t need = ffp_lu_nopiv_workspace(m, n, p, path);
+    if (!ws || ws_bytes < need) return FFP_E_WORKSPACE;
+    Field F(p);
+    Arena ar;
+    ar.base = (char *)ws;
+    ar.cap = ws_bytes;
+    return lu_nopiv_run(path, F, m, n, A, lda, (int *)info_dev, ar, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------ check_range
+int ffp_check_range(int64_t m, int64_t n, uint32_t p, const int32_t *A, int64_t lda, ffp_stream_t stream) {
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (p < 2) return -3;
+    if (m > 0 && n > 0 && !A) return -4;
+    if (lda < (n > 1 ? n : 1)) return -5;
+    bool ok = true;
+    FFP_CHECK(check_range_run(m, n, p, A, lda, (hipStream_t)stream, &ok));
+    return ok ? FFP_OK : FFP_E_RANGE;
+}
+
 // ------------------------------------------------------------------ batched
 size_t ffp_pluq_batched_workspace(int32_t batch, int32_t max_m, int32_t max_n, uint32_t p, int path) {
     (void)p;
@@ -373,5 +410,6 @@ int ffp_profile_read(int path, int64_t *launches, double *milliseconds, double *
     return profile_read(path, launches, milliseconds, field_ops);
 }
 int ffp_profile_read_bytes(int path, double *bytes) { return profile_read_bytes(path, bytes); }
+const char *ffp_profile_kind_name(int kind) { return profile_kind_name(kind); }
 
 }  // extern "C"

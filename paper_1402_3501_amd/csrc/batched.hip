@@ -158,7 +158,8 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
                                                       const int64_t *__restrict__ Q_off, int32_t *__restrict__ rank,
                                                       int32_t *__restrict__ rrp, int32_t *__restrict__ crp,
                                                       int *__restrict__ counter, int32_t *__restrict__ slots,
-                                                      int64_t slot_elems, double p, double pinv, int32_t half) {
+                                                      int64_t slot_elems, int32_t max_m, int32_t max_n, double p,
+                                                      double pinv, int32_t half) {
     __shared__ BShared S;
     const int tid = threadIdx.x;
     int32_t *W = slots + (int64_t)blockIdx.x * slot_elems;
@@ -168,6 +169,13 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
         const int job = S.job;
         if (job >= batch) break;  // uniform: every wave of the workgroup exits
         const int m = m_arr[job], n = n_arr[job];
+        // a shape beyond the bounds the workspace slots and the LDS masks were
+        // sized for is not factored: its rank reads -1 (uniform branch)
+        if (m < 0 || n < 0 || m > max_m || n > max_n) {
+            if (tid == 0) rank[job] = -1;
+            __syncthreads();
+            continue;
+        }
         int32_t *Aj = A + A_off[job];
         const int nwr = (m + 31) >> 5, nwc = (n + 31) >> 5;
         // workspace copy (leading dimension n), and the nonzero-row mask
@@ -420,9 +428,11 @@ static int launch_shape(int shape, const Field &F, int32_t batch, const int32_t 
     if (!counter || !slots) return FFP_E_WORKSPACE;
     // counter cleared by a kernel (not a memset) so that the sequence can be captured in a graph
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, counter);
+    ProfScope prof(PK_BATCHED, 0.0, s, 0.0);
 #define FFP_BAT(T_)                                                                                          \
     hipLaunchKernelGGL((k_pluq_batched<T_>), dim3(grid), dim3(T_), 0, s, batch, m_arr, n_arr, A, A_off, P, P_off, \
-                       Q, Q_off, rank, rrp, crp, counter, slots, slot, F.pd, F.pinv, (int32_t)F.half)
+                       Q, Q_off, rank, rrp, crp, counter, slots, slot, max_m, max_n, F.pd, F.pinv, \
+                       (int32_t)F.half)
     if (kShapes[shape].threads == 1024) FFP_BAT(1024);
     else FFP_BAT(256);
 #undef FFP_BAT

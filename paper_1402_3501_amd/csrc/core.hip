@@ -89,7 +89,7 @@ void *Arena::take(size_t bytes) {
 // ------------------------------------------------------------------ profiling
 namespace {
 struct ProfRec {
-    int path;
+    int kind;
     double ops, bytes;
     hipEvent_t e0, e1;
 };
@@ -100,7 +100,7 @@ std::vector<hipEvent_t> g_pool;  // recycled events (creation is the costly part
 struct ProfTotals {
     int64_t launches = 0;
     double ms = 0.0, ops = 0.0, bytes = 0.0;
-} g_tot[3];
+} g_tot[kProfKinds];
 
 hipEvent_t pool_get() {
     if (!g_pool.empty()) {
@@ -118,11 +118,11 @@ void drain_locked() {
         float ms = 0.f;
         (void)hipEventSynchronize(r.e1);
         (void)hipEventElapsedTime(&ms, r.e0, r.e1);
-        if (r.path >= 0 && r.path < 3) {
-            g_tot[r.path].launches += 1;
-            g_tot[r.path].ms += ms;
-            g_tot[r.path].ops += r.ops;
-            g_tot[r.path].bytes += r.bytes;
+        if (r.kind >= 0 && r.kind < kProfKinds) {
+            g_tot[r.kind].launches += 1;
+            g_tot[r.kind].ms += ms;
+            g_tot[r.kind].ops += r.ops;
+            g_tot[r.kind].bytes += r.bytes;
         }
         g_pool.push_back(r.e0);
         g_pool.push_back(r.e1);
@@ -131,8 +131,8 @@ void drain_locked() {
 }
 }  // namespace
 
-ProfScope::ProfScope(int path_, double ops_, hipStream_t s_, double bytes_)
-    : path(path_), ops(ops_), bytes(bytes_), s(s_) {
+ProfScope::ProfScope(int kind_, double ops_, hipStream_t s_, double bytes_)
+    : kind(kind_), ops(ops_), bytes(bytes_), s(s_) {
     if (!g_prof_on) return;
     std::lock_guard<std::mutex> g(g_prof_mu);
     hipEvent_t a = pool_get(), b = pool_get();
@@ -150,7 +150,7 @@ ProfScope::~ProfScope() {
     if (!ev0) return;
     (void)hipEventRecord((hipEvent_t)ev1, s);
     std::lock_guard<std::mutex> g(g_prof_mu);
-    g_prof.push_back({path, ops, bytes, (hipEvent_t)ev0, (hipEvent_t)ev1});
+    g_prof.push_back({kind, ops, bytes, (hipEvent_t)ev0, (hipEvent_t)ev1});
 }
 
 int profile_enable(int on) {
@@ -164,21 +164,35 @@ int profile_reset() {
     for (auto &t : g_tot) t = ProfTotals();
     return FFP_OK;
 }
-int profile_read(int path, int64_t *launches, double *ms, double *ops) {
+int profile_read(int kind, int64_t *launches, double *ms, double *ops) {
     std::lock_guard<std::mutex> g(g_prof_mu);
     drain_locked();
-    if (path < 0 || path > 2) return -1;
-    if (launches) *launches = g_tot[path].launches;
-    if (ms) *ms = g_tot[path].ms;
-    if (ops) *ops = g_tot[path].ops;
+    if (kind < 0 || kind >= kProfKinds) return -1;
+    if (launches) *launches = g_tot[kind].launches;
+    if (ms) *ms = g_tot[kind].ms;
+    if (ops) *ops = g_tot[kind].ops;
     return FFP_OK;
 }
-int profile_read_bytes(int path, double *bytes) {
+int profile_read_bytes(int kind, double *bytes) {
     std::lock_guard<std::mutex> g(g_prof_mu);
     drain_locked();
-    if (path < 0 || path > 2) return -1;
-    if (bytes) *bytes = g_tot[path].bytes;
+    if (kind < 0 || kind >= kProfKinds) return -1;
+    if (bytes) *bytes = g_tot[kind].bytes;
     return FFP_OK;
+}
+const char *profile_kind_name(int kind) {
+    static const char *names[kProfKinds] = {"",
+                                            "k_fgemm_f64",
+                                            "k_fgemm_i8",
+                                            "k_split",
+                                            "k_i8_combine",
+                                            "k_leaf_gen",
+                                            "k_leaf64",
+                                            "k_trsm",
+                                            "k_permute",
+                                            "k_pluq_batched",
+                                            "k_winograd_add"};
+    return kind > 0 && kind < kProfKinds ? names[kind] : nullptr;
 }
 
 // ------------------------------------------------------------------ scaling
@@ -227,6 +241,7 @@ int permute_copy(int64_t m, int64_t n, const int32_t *src, int64_t lds, int32_t 
     if (m <= 0 || n <= 0) return FFP_OK;
     unsigned gx = (unsigned)((n + 255) / 256);
     if (gx > 16) gx = 16;
+    ProfScope prof(PK_PERMUTE, 0.0, s, 8.0 * (double)m * (double)n);
     for (int64_t r0 = 0; r0 < m; r0 += 65535) {
         int64_t rows = m - r0 < 65535 ? m - r0 : 65535;
         hipLaunchKernelGGL(k_permute, dim3(gx, (unsigned)rows), dim3(256), 0, s, m, n, src, lds, dst, ldd,
@@ -266,6 +281,7 @@ int permute_inplace(int64_t m, int64_t n, int32_t *A, int64_t lda, const PermSpe
     if (m <= 0 || n <= 0 || (rp.identity() && cp.identity())) return FFP_OK;
     if (m * n <= kPermLds) {
         if (ws.counting) return FFP_OK;
+        ProfScope prof(PK_PERMUTE, 0.0, s, 8.0 * (double)m * (double)n);
         hipLaunchKernelGGL(k_permute_lds, dim3(1), dim3(1024), (size_t)(m * n) * 4, s, m, n, A, lda, rp, cp);
         FFP_HIP_CHECK(hipGetLastError());
         return FFP_OK;

@@ -55,14 +55,33 @@ struct Arena {
 };
 
 // ------------------------------------------------------------------ profiling
+// Kernel families timed by the optional launch events (ffp_profile_*): each
+// launch site brackets its kernel with a ProfScope of its family, giving
+// the launch's algorithmic work (field operations: 2 m n k for a product,
+// d^2 nv for a triangular solve, 2 m n k - (m + n) k^2 + 2 k^3 / 3 for an
+// elimination of rank k) and its algorithmic bytes.
+enum ProfKind {
+    PK_FGEMM_F64 = 1,   // FP64 matrix-core products (all shapes)
+    PK_FGEMM_I8 = 2,    // INT8 matrix-core products (the product kernel alone)
+    PK_I8_SPLIT = 3,    // limb split of the INT8 operands
+    PK_I8_COMBINE = 4,  // split-K combining pass
+    PK_LEAF_GEN = 5,    // generic-rank-profile leaves (with their fused solves / update)
+    PK_LEAF = 6,        // leaves of the general recursion
+    PK_TRSM = 7,        // triangular-solve base cases and block inverses
+    PK_PERMUTE = 8,     // out-of-place and in-LDS permutations
+    PK_BATCHED = 9,     // the persistent batched factorisation
+    PK_WINOGRAD = 10,   // pre- and post-additions of the Strassen-Winograd products
+};
+constexpr int kProfKinds = 11;
 struct ProfScope {
-    int path;
+    int kind;
     double ops, bytes;
     hipStream_t s;
     void *ev0 = nullptr, *ev1 = nullptr;
-    ProfScope(int path_, double ops_, hipStream_t s_, double bytes_ = 0.0);
+    ProfScope(int kind_, double ops_, hipStream_t s_, double bytes_ = 0.0);
     ~ProfScope();
 };
+const char *profile_kind_name(int kind);
 
 // ------------------------------------------------------------------ kernels (launchers)
 // All return FFP_OK or an error code; all are asynchronous on `s`.
@@ -159,6 +178,12 @@ int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda,
 int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P,
              int32_t *Q, int64_t *r, Arena &ws, hipStream_t s);
 size_t pluq_ws(int64_t m, int64_t n, const Field &F, int path);
+// plain LU of a generic-rank-profile input, asynchronous; *info (device) = 0
+// or 1 + the diagonal index of the first zero pivot
+int lu_nopiv_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int *info, Arena &ws,
+                 hipStream_t s);
+// *ok = every entry of the block lies in [0, p) (synchronises s)
+int check_range_run(int64_t m, int64_t n, uint32_t p, const int32_t *A, int64_t lda, hipStream_t s, bool *ok);
 // sorted rank profiles from P[0:r] (device); r is a host value
 int rank_profiles(int64_t m, int64_t n, const int32_t *P, const int32_t *Q, int64_t r,
                   int32_t *rrp, int32_t *crp, Arena &ws, hipStream_t s);

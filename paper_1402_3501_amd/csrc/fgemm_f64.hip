@@ -529,7 +529,7 @@ int fgemm_f64_pair(const Field &F, int64_t m0, int64_t n0, const int32_t *A0, in
     };
     const SkOp o0 = op(m0, n0, A0, lda0, B0, ldb0, C0, ldc0), o1 = op(m1, n1, A1, lda1, B1, ldb1, C1, ldc1);
     const double mn = (double)m0 * (double)n0 + (double)m1 * (double)n1;
-    ProfScope prof(FFP_PATH_FP64, 2.0 * mn * (double)k, s,
+    ProfScope prof(PK_FGEMM_F64, 2.0 * mn * (double)k, s,
                    4.0 * ((double)(m0 + m1) * (double)k + (double)k * (double)(n0 + n1) + (beta != 0 ? 2.0 : 1.0) * mn));
     const dim3 grid((unsigned)(o0.nblk + o1.nblk));
     if (red)
@@ -551,7 +551,7 @@ int fgemm_f64(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, u
     const double p = F.pd, pinv = F.pinv, a = (double)alpha, b = (double)beta;
     const int32_t half = (int32_t)F.half;
     const int64_t big_tiles = ((m + 127) / 128) * ((n + 127) / 128);
-    ProfScope prof(FFP_PATH_FP64, 2.0 * (double)m * (double)n * (double)k, s,
+    ProfScope prof(PK_FGEMM_F64, 2.0 * (double)m * (double)n * (double)k, s,
                    4.0 * ((double)m * (double)k + (double)k * (double)n + (beta != 0 ? 2.0 : 1.0) * (double)m * (double)n));
     if (big_tiles >= 192) {
         dim3 grid((unsigned)((n + 127) / 128), (unsigned)((m + 127) / 128));

@@ -320,8 +320,11 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
         const int64_t asr = ta ? 1 : lda, ask = ta ? lda : 1;
         const int64_t bsr = tb ? ldb : 1, bsk = tb ? 1 : ldb;
         const SplitSrc sa{Ab, asr, ask, m, planeA, Ad}, sb{Bb, bsr, bsk, n, planeB, Bd};
-        hipLaunchKernelGGL((k_split<L>), dim3((unsigned)(Kp / 64), (unsigned)((Mp + Np) / 64)), dim3(256), 0, s, sa,
-                           sb, Mp / 64, kc, Kp, (int32_t)F.half, (int32_t)F.p);
+        {
+            ProfScope prof(PK_I8_SPLIT, 0.0, s, 4.0 * (double)kc * (double)(m + n) + (double)L * (double)Kp * (double)(Mp + Np));
+            hipLaunchKernelGGL((k_split<L>), dim3((unsigned)(Kp / 64), (unsigned)((Mp + Np) / 64)), dim3(256), 0, s,
+                               sa, sb, Mp / 64, kc, Kp, (int32_t)F.half, (int32_t)F.p);
+        }
         const double be = kc0 == 0 ? (double)beta : 1.0;
         const int ntx = (int)(Np / kI8BN), nty = (int)(Mp / kI8BM);
         const int64_t nt = Kp / kI8BK;
@@ -339,15 +342,19 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
             kt_per = nt;
         }
         {
-            ProfScope prof(FFP_PATH_INT8, 2.0 * (double)m * (double)n * (double)kc, s,
-                           4.0 * ((double)m * (double)kc + (double)kc * (double)n +
-                                  (be != 0.0 ? 2.0 : 1.0) * (double)m * (double)n));
+            // algorithmic bytes: the limb planes read once, the result written
+            // once (and C read once when beta != 0)
+            ProfScope prof(PK_FGEMM_I8, 2.0 * (double)m * (double)n * (double)kc, s,
+                           (double)L * ((double)m * (double)kc + (double)kc * (double)n) +
+                               4.0 * (part ? (double)nz : (be != 0.0 ? 2.0 : 1.0)) * (double)m * (double)n);
             hipLaunchKernelGGL((k_fgemm_i8<L>), dim3((unsigned)(ntx * nty * nz)), dim3(kI8Threads), 0, s, Ad, Bd, Kp,
                                planeA, planeB, m, n, C, ldc, F.pd, F.pinv, (double)alpha, be, wts[0], wts[1],
                                wts[2], wts[3], ntx, nty, kt_per, part);
-            if (part)
-                hipLaunchKernelGGL(k_i8_combine, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0, s, m, n,
-                                   nz, part, C, ldc, F.pd, F.pinv, (double)alpha, be);
+        }
+        if (part) {
+            ProfScope prof(PK_I8_COMBINE, 0.0, s, 4.0 * ((double)nz + (be != 0.0 ? 2.0 : 1.0)) * (double)m * (double)n);
+            hipLaunchKernelGGL(k_i8_combine, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0, s, m, n,
+                               nz, part, C, ldc, F.pd, F.pinv, (double)alpha, be);
         }
         FFP_HIP_CHECK(hipGetLastError());
         ws.release(mk);

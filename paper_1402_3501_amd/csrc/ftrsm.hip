@@ -434,6 +434,7 @@ static int trsm_blk(const Field &F, int side, int d, int64_t nv, const int32_t *
     const bool red = F.kexact < kTB;
     const int ksteps = (int)(F.kexact / 4 < 1 ? 1 : (F.kexact / 4 > 16 ? 16 : F.kexact / 4));
     dim3 grid((unsigned)((nv + kVB - 1) / kVB));
+    ProfScope prof(PK_TRSM, (double)d * (double)d * (double)nv, s, 4.0 * (double)d * (double)d / 2.0 + 8.0 * (double)d * (double)nv);
 #define FFP_TBK(L_, R_)                                                                                          \
     hipLaunchKernelGGL((k_trsm_blk<L_, R_>), grid, dim3(256), 0, s, d, nv, T, ldt, (int)direct, (int)fwd, W, B, ldb, \
                        F.pd, F.pinv, (int32_t)F.half, ksteps)
@@ -456,6 +457,7 @@ static int trsm_apply(const Field &F, int side, int db, int64_t nv, const double
     const bool red = F.kexact < db;
     const int ksteps = (int)(F.kexact / 4 < 1 ? 1 : (F.kexact / 4 > 16 ? 16 : F.kexact / 4));
     dim3 grid((unsigned)((nv + kTB - 1) / kTB));
+    ProfScope prof(PK_TRSM, (double)db * (double)db * (double)nv, s, 8.0 * (double)db * (double)nv);
 #define FFP_TA(L_, R_)                                                                                    \
     hipLaunchKernelGGL((k_trsm_apply<L_, R_>), grid, dim3(256), 0, s, db, nv, W, B, ldb, F.pd, F.pinv, \
                        (int32_t)F.half, ksteps)
@@ -539,6 +541,7 @@ int ftrsm_run(int path, const Field &F, int side, int uplo, int trans, int diag,
     // dot products of the inversion take at most 32 terms
     const bool red = F.kexact < 32;
     const int kchunk = (int)(F.kexact < 1 ? 1 : (F.kexact > 32 ? 32 : F.kexact));
+    ProfScope prof(PK_TRSM, 0.0, s, 4.0 * (double)d * (double)d / 2.0 + 8.0 * (double)nblk * kTB * kTB);
 #define FFP_TI(R_)                                                                                          \
     hipLaunchKernelGGL((k_trsm_inv<R_>), dim3((unsigned)nblk), dim3(256), 0, s, d, T, ldt, uplo, diag, \
                        (int)eff_lower, W, F.pd, F.pinv, (int32_t)F.half, kchunk)
@@ -563,6 +566,8 @@ static int trsm_pair_base(const Field &F, int64_t h, const int32_t *T, int64_t l
                           int64_t nve, int32_t *Be, int64_t ldb, const double *Li, const double *Ui, hipStream_t s) {
     if (h <= 0 || h > kTBB || (nvd <= 0 && nve <= 0)) return FFP_OK;
     const int ksteps = (int)(F.kexact / 4 < 1 ? 1 : (F.kexact / 4 > 16 ? 16 : F.kexact / 4));
+    ProfScope prof(PK_TRSM, (double)h * (double)h * (double)(nvd + nve), s,
+                   4.0 * (double)h * (double)h + 8.0 * (double)h * (double)(nvd + nve));
     if (h <= kTB) {
         const bool red = F.kexact < h;
         const int gd = (int)((nvd + kTB - 1) / kTB), ge = (int)((nve + kTB - 1) / kTB);

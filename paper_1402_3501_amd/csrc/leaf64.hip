@@ -645,11 +645,18 @@ int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda,
     hipLaunchKernelGGL((k_leaf_gen<S_, kGenWaves, L_>), dim3(1), dim3(64 * kGenWaves), 0, s, (int)m, (int)n, A, lda, \
                        F.pd, F.pinv, (int32_t)F.half, gflag, Linv, Uinv, inv_red, kchunk, He, Hd, Pd, (int)pdn, Pe,   \
                        (int)pem, (int)diag0)
+        const double kk = (double)(m < n ? m : n);
+        ProfScope prof(PK_LEAF_GEN,
+                       2.0 * (double)m * (double)n * kk - (double)(m + n) * kk * kk + 2.0 * kk * kk * kk / 3.0 +
+                           (He ? 2.0 * (double)m * (double)n * 64.0 : 0.0) +
+                           (Pd ? 64.0 * 64.0 * (double)(pdn + pem) : 0.0),
+                       s, 8.0 * (double)m * (double)n);
         if (lazy) FFP_LG(true, true);
         else if (small) FFP_LG(true, false);
         else FFP_LG(false, false);
 #undef FFP_LG
     } else {
+        ProfScope prof(PK_LEAF, 0.0, s, 8.0 * (double)m * (double)n);
         FFP_SEL(FFP_L64)
     }
 #undef FFP_SEL

@@ -665,6 +665,7 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
     }
     if (leaf_fits(m, n)) {
         const bool red = F.kexact < kLMaxDim;
+        ProfScope prof(PK_LEAF, 0.0, s, 8.0 * (double)m * (double)n);
         if (red)
             hipLaunchKernelGGL((k_pluq_leaf<true>), dim3(1), dim3(kLT), 0, s, (int)m, (int)n, A, lda, P, Q,
                                c.rank_dev, F.pd, F.pinv, (int32_t)F.half, F.kexact);
@@ -936,6 +937,56 @@ int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t
         }
     }
     return pluq_rec(c, m, n, A, lda, P, Q, r, gen_ok);
+}
+
+// Plain LU of an input of generic rank profile, asynchronous (ffp_lu_nopiv):
+// the generic attempt without its checkpoints (they read the flag back) and
+// without the backup copy; *info = 1 + the first zero pivot's diagonal index.
+int lu_nopiv_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int *info, Arena &ws,
+                 hipStream_t s) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, info, 0);
+    FFP_HIP_CHECK(hipGetLastError());
+    if (m == 0 || n == 0) return FFP_OK;
+    const size_t mk = ws.mark();
+    const size_t nblk = (size_t)(((m < n ? m : n) + 63) / 64);
+    double *Li = (double *)ws.take(nblk * kBlk * sizeof(double));
+    double *Ui = (double *)ws.take(nblk * kBlk * sizeof(double));
+    if (!Li || !Ui) return FFP_E_WORKSPACE;
+    Ctx c{path, &F, &ws, s, nullptr, nullptr, info};
+    c.gen_k = 0;
+    FFP_CHECK(lu_generic(c, m, n, A, lda, info, Li, Ui, 0));
+    ws.release(mk);
+    return FFP_OK;
+}
+
+// ffp_check_range: one pass over the block, any entry outside [0, p) stores
+// 1 into a pinned host word (all writers store the same value)
+__global__ __launch_bounds__(256) void k_range(int64_t m, int64_t n, const int32_t *__restrict__ A, int64_t lda,
+                                               int32_t p, int64_t *__restrict__ word) {
+    bool bad = false;
+    for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
+        const int32_t *row = A + i * lda;
+        for (int64_t j = threadIdx.x; j < n; j += 256) bad |= (uint32_t)row[j] >= (uint32_t)p;
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) *(volatile int64_t *)word = 1;
+}
+
+int check_range_run(int64_t m, int64_t n, uint32_t p, const int32_t *A, int64_t lda, hipStream_t s, bool *ok) {
+    *ok = true;
+    if (m <= 0 || n <= 0) return FFP_OK;
+    RankWord rw;
+    FFP_CHECK(rank_word_get(&rw));
+    struct WordBack {
+        RankWord w;
+        ~WordBack() { rank_word_put(w); }
+    } word_back{rw};
+    *(volatile int64_t *)rw.host = 0;
+    const unsigned g = (unsigned)(m < 2048 ? m : 2048);
+    hipLaunchKernelGGL(k_range, dim3(g), dim3(256), 0, s, m, n, A, lda, (int32_t)p, rw.dev);
+    FFP_HIP_CHECK(hipGetLastError());
+    FFP_HIP_CHECK(hipStreamSynchronize(s));
+    *ok = *(const volatile int64_t *)rw.host == 0;
+    return FFP_OK;
 }
 
 // ===================================================================== rank profiles

@@ -76,7 +76,7 @@ def test_argument_validation_before_device(lib):
     assert lib.ffp_fgemm(0, 0, 4, 5, 3, 7, 1, fake, 3, fake, 4, 0, fake, 5, 0, None, 0, None) == -11
     assert lib.ffp_fgemm(0, 0, 4, 5, 3, 7, 1, fake, 3, fake, 5, 0, fake, 4, 0, None, 0, None) == -14
     # bad path
-    assert lib.ffp_fgemm(0, 0, 4, 4, 4, 7, 1, fake, 4, fake, 4, 0, fake, 4, 5, None, 0, None) == -16
+    assert lib.ffp_fgemm(0, 0, 4, 4, 4, 7, 1, fake, 4, fake, 4, 0, fake, 4, 5, None, 0, None) == -15
     # empty problems succeed without touching memory
     assert lib.ffp_fgemm(0, 0, 0, 4, 4, 7, 1, None, 4, None, 4, 0, None, 4, 0, None, 0, None) == 0
     # ftrsm
@@ -99,6 +99,17 @@ def test_argument_validation_before_device(lib):
                                 None, 0, None, 0, None) == -1
     assert lib.ffp_pluq_batched(3, fake, fake, 2000, 4, 7, fake, fake, fake, fake, fake, fake, fake, None,
                                 None, 0, None, 0, None) == -4
+    # lu_nopiv
+    assert lib.ffp_lu_nopiv(4, 4, 9, fake, 4, fake, 0, None, 0, None) == -101
+    assert lib.ffp_lu_nopiv(4, 4, 7, fake, 4, fake, 4, None, 0, None) == -7
+    assert lib.ffp_lu_nopiv(4, 4, 7, fake, 3, fake, 0, None, 0, None) == -5
+    assert lib.ffp_lu_nopiv(4, 4, 7, fake, 4, None, 0, None, 0, None) == -6
+    assert lib.ffp_lu_nopiv(4, 4, 7, fake, 4, fake, 0, None, 0, None) == -103
+    # check_range
+    assert lib.ffp_check_range(-1, 4, 7, fake, 4, None) == -1
+    assert lib.ffp_check_range(4, 4, 1, fake, 4, None) == -3
+    assert lib.ffp_check_range(4, 4, 7, fake, 3, None) == -5
+    assert lib.ffp_check_range(0, 4, 7, None, 4, None) == 0
 
 
 def test_workspace_queries(lib):

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import checks
-from paper_1402_3501_amd import workloads as wl
+import workloads as wl
 
 pytestmark = pytest.mark.gpu
 

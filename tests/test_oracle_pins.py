@@ -12,7 +12,7 @@ import pytest
 
 import blockref
 import checks
-from paper_1402_3501_amd import workloads as wl
+import workloads as wl
 
 PRIMES = [2, 3, 5, 7, 251, 65521, 131071, 8388593]
 
