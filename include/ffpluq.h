@@ -49,6 +49,7 @@ typedef void *ffp_stream_t; /* hipStream_t */
 #define FFP_E_UNSUPPORTED (-106) /* valid request this build does not implement */
 #define FFP_E_NODEVICE (-107)    /* no gfx950 device / kernels failed to load */
 #define FFP_E_INTERNAL (-108)    /* internal consistency check failed; A is restored */
+#define FFP_E_SCRATCH (-109)     /* request exceeds the fixed scratch of ffp_fgemm_noalloc */
 
 /* Largest p of each arithmetic path (see ffp_fgemm). */
 #define FFP_P_MAX_FP64 94906249u /* largest prime with (p-1)^2 + p < 2^53 */
@@ -92,6 +93,26 @@ size_t ffp_fgemm_workspace(int transA, int transB, int64_t m, int64_t n, int64_t
 int ffp_fgemm(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t p, uint32_t alpha,
               const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta, int32_t *C,
               int64_t ldc, int path, void *ws, size_t ws_bytes, ffp_stream_t stream);
+
+/* --------------------------------------------------------------------------
+ * fgemm_noalloc -- for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, hosts that forbid
+ * allocation): the same product as ffp_fgemm, same arguments and the same
+ * bits, minus the workspace.  The INT8 path takes its limb planes (and
+ * split-K partial results) from a fixed device array of
+ * FFP_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends; the call itself never allocates or frees.
+ *   An INT8 product whose ffp_fgemm_workspace exceeds that size returns
+ *   FFP_E_SCRATCH (nothing is launched); with FFP_PATH_AUTO such a product
+ *   runs on the FP64 path instead (no workspace, same result).
+ * All calls on one GPU share the array, so calls that overlap on one GPU
+ * (different streams or host threads) race: the caller serialises them.
+ * -------------------------------------------------------------------------- */
+#define FFP_NOALLOC_SCRATCH_BYTES (64u << 20)
+size_t ffp_noalloc_scratch_bytes(void);
+int ffp_fgemm_noalloc(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t p, uint32_t alpha,
+                      const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta, int32_t *C,
+                      int64_t ldc, int path, ffp_stream_t stream);
 
 /* --------------------------------------------------------------------------
  * ftrsm -- Section 2.1 (trsm): triangular solve mod p.

@@ -52,6 +52,8 @@ def load():
         "ffp_auto_path": ([u32, i64, i64, i64], i32),
         "ffp_fgemm_workspace": ([i32, i32, i64, i64, i64, u32, i32], sz),
         "ffp_fgemm": ([i32, i32, i64, i64, i64, u32, u32, vp, i64, vp, i64, u32, vp, i64, i32, vp, sz, vp], i32),
+        "ffp_fgemm_noalloc": ([i32, i32, i64, i64, i64, u32, u32, vp, i64, vp, i64, u32, vp, i64, i32, vp], i32),
+        "ffp_noalloc_scratch_bytes": ([], sz),
         "ffp_ftrsm_workspace": ([i32, i32, i32, i32, i64, i64, u32, i32], sz),
         "ffp_ftrsm": ([i32, i32, i32, i32, i64, i64, u32, u32, vp, i64, vp, i64, i32, vp, sz, vp], i32),
         "ffp_flaswp_workspace": ([i32, i64, i64], sz),

@@ -63,6 +63,28 @@ __global__ void k_invperm(const int32_t *__restrict__ perm, int64_t n, int32_t *
         inv[perm[i]] = (int32_t)i;
 }
 
+// Argument checks of ffp_fgemm (LAPACK numbering of its arguments), shared
+// with the allocation-free variant; *eff = the path the product runs on.
+int fgemm_validate(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t p, uint32_t alpha,
+                   const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta, const int32_t *C,
+                   int64_t ldc, int path, int *eff) {
+    if (transA != 0 && transA != 1) return -1;
+    if (transB != 0 && transB != 1) return -2;
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (k < 0) return -5;
+    FFP_CHECK(check_field(p, path, 6, 15));
+    if (alpha >= p) return -7;
+    if (beta >= p) return -12;
+    *eff = resolve_path(path, p, m, n, k);
+    if (m == 0 || n == 0) return FFP_OK;
+    const int64_t acols = transA ? m : k, bcols = transB ? k : n;
+    if (k > 0 && (!A || lda < (acols > 1 ? acols : 1))) return A ? -9 : -8;
+    if (k > 0 && (!B || ldb < (bcols > 1 ? bcols : 1))) return B ? -11 : -10;
+    if (!C || ldc < (n > 1 ? n : 1)) return C ? -14 : -13;
+    return FFP_OK;
+}
+
 }  // namespace ffp
 
 using namespace ffp;
@@ -80,6 +102,7 @@ const char *ffp_error_string(int code) {
         case FFP_E_UNSUPPORTED: return "unsupported request";
         case FFP_E_NODEVICE: return "no usable gfx950 device";
         case FFP_E_INTERNAL: return "internal consistency check failed";
+        case FFP_E_SCRATCH: return "request exceeds the fixed scratch of the allocation-free entry point";
         default: return code < 0 && code > -64 ? "invalid argument" : "unknown error";
     }
 }
@@ -108,20 +131,9 @@ size_t ffp_fgemm_workspace(int transA, int transB, int64_t m, int64_t n, int64_t
 int ffp_fgemm(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t p, uint32_t alpha,
               const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta, int32_t *C,
               int64_t ldc, int path, void *ws, size_t ws_bytes, ffp_stream_t stream) {
-    if (transA != 0 && transA != 1) return -1;
-    if (transB != 0 && transB != 1) return -2;
-    if (m < 0) return -3;
-    if (n < 0) return -4;
-    if (k < 0) return -5;
-    FFP_CHECK(check_field(p, path, 6, 15));
-    if (alpha >= p) return -7;
-    if (beta >= p) return -12;
+    int eff = 0;
+    FFP_CHECK(fgemm_validate(transA, transB, m, n, k, p, alpha, A, lda, B, ldb, beta, C, ldc, path, &eff));
     if (m == 0 || n == 0) return FFP_OK;
-    const int64_t acols = transA ? m : k, bcols = transB ? k : n;
-    if (k > 0 && (!A || lda < (acols > 1 ? acols : 1))) return A ? -9 : -8;
-    if (k > 0 && (!B || ldb < (bcols > 1 ? bcols : 1))) return B ? -11 : -10;
-    if (!C || ldc < (n > 1 ? n : 1)) return C ? -14 : -13;
-    const int eff = resolve_path(path, p, m, n, k);
     const size_t need = ffp_fgemm_workspace(transA, transB, m, n, k, p, eff);
     if (need > 0 && (!ws || ws_bytes < need)) return FFP_E_WORKSPACE;
     Field F(p);

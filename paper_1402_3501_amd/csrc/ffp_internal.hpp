@@ -111,6 +111,11 @@ int fgemm_any(int path, const Field &F, int ta, int tb, int64_t m, int64_t n, in
               uint32_t alpha, const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb,
               uint32_t beta, int32_t *C, int64_t ldc, Arena &ws, hipStream_t s);
 int resolve_path(int path, uint32_t p, int64_t m, int64_t n, int64_t k);
+// argument checks of ffp_fgemm (negative argument index or FFP_E_*), and the
+// path the product runs on
+int fgemm_validate(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t p, uint32_t alpha,
+                   const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta, const int32_t *C,
+                   int64_t ldc, int path, int *eff);
 
 // triangular solve (recursive onto fgemm_any); alpha applied first
 int ftrsm_run(int path, const Field &F, int side, int uplo, int trans, int diag, int64_t m,
