@@ -95,6 +95,30 @@ int ffp_fgemm(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t 
               int64_t ldc, int path, void *ws, size_t ws_bytes, ffp_stream_t stream);
 
 /* --------------------------------------------------------------------------
+ * fgemm_wino -- Section 2.1: the sequential fgemm runs recursive steps of
+ * Winograd's variant of Strassen's algorithm over the plain product
+ * (Sections 2.3 and 3.2 discuss its gain and crossover).  Same arguments and
+ * the same result as ffp_fgemm, plus:
+ *   levels: number of Winograd steps (0 = the plain product, at most
+ *     FFP_WINO_MAX_LEVELS), or FFP_WINO_AUTO for the levels this library
+ *     measured to pay on MI355X for the size and path.
+ * Each step splits op(A), op(B), C into 2 x 2 blocks (odd dimensions peeled
+ * off and finished by thin products) and forms C from 7 block products and
+ * 15 block additions; every addition is reduced mod p as it is formed, so
+ * the block products keep the exactness bound of the plain product.
+ * Temporaries (4 (m k + k n + m n) / 4 int32 per step) come from the
+ * workspace, ffp_fgemm_wino_workspace bytes.  An invalid `levels` is
+ * argument 16.
+ * -------------------------------------------------------------------------- */
+#define FFP_WINO_AUTO (-1)
+#define FFP_WINO_MAX_LEVELS 6
+size_t ffp_fgemm_wino_workspace(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t p, int path,
+                                int levels);
+int ffp_fgemm_wino(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t p, uint32_t alpha,
+                   const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta, int32_t *C,
+                   int64_t ldc, int path, int levels, void *ws, size_t ws_bytes, ffp_stream_t stream);
+
+/* --------------------------------------------------------------------------
  * fgemm_noalloc -- for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, hosts that forbid
  * allocation): the same product as ffp_fgemm, same arguments and the same
@@ -203,6 +227,41 @@ int ffp_pluq(int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int32_t 
 size_t ffp_lu_nopiv_workspace(int64_t m, int64_t n, uint32_t p, int path);
 int ffp_lu_nopiv(int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int32_t *info_dev, int path,
                  void *ws, size_t ws_bytes, ffp_stream_t stream);
+
+/* --------------------------------------------------------------------------
+ * Consumers of the rank profile (Section 1, "Pivoting strategies and rank
+ * deficiencies": the pivoting that reveals the rank profile reveals the
+ * echelon form).  They take the output of ffp_pluq as it stands: LU (m x n,
+ * leading dimension ld, L\U in place), P (m), Q (n) and the rank r (host
+ * value), all device memory, none modified.  Asynchronous on `stream`; the
+ * workspace queries give the bytes each call takes.
+ *
+ * echelon -- form 0: the reduced row echelon form of A, E (r x n, leading
+ *   dimension lde >= n): E[:, crp] = I, row t has its leading 1 in column
+ *   crp[t] (the column rank profile, ascending), and the rows span the row
+ *   space of A.  form 1: the reduced column echelon form, E (m x r, lde >=
+ *   r), the transpose of the row form of A^T: E[rrp, :] = I.
+ * nullspace -- side 0: N (n x (n - r), ldn >= n - r) with A N = 0 and N = I
+ *   on the non-pivot columns (ascending); side 1: N ((m - r) x m, ldn >= m)
+ *   with N A = 0 and N = I on the non-pivot rows.  Both bases are unique.
+ * solve -- A X = B for B (m x nrhs, ldb >= nrhs): consistent[j] (device
+ *   int32[nrhs]) = 1 when column j of B lies in the column space of A, and
+ *   then X[:, j] (X is n x nrhs, ldx >= nrhs) is the solution that is zero
+ *   on the non-pivot columns; otherwise consistent[j] = 0 and X[:, j] = 0.
+ * Arguments are numbered from form / side = 1 (ffp_solve from m = 1).
+ * -------------------------------------------------------------------------- */
+size_t ffp_echelon_workspace(int form, int64_t m, int64_t n, int64_t r, uint32_t p, int path);
+int ffp_echelon(int form, int64_t m, int64_t n, uint32_t p, const int32_t *LU, int64_t ld, const int32_t *P,
+                const int32_t *Q, int64_t r, int32_t *E, int64_t lde, int path, void *ws, size_t ws_bytes,
+                ffp_stream_t stream);
+size_t ffp_nullspace_workspace(int side, int64_t m, int64_t n, int64_t r, uint32_t p, int path);
+int ffp_nullspace(int side, int64_t m, int64_t n, uint32_t p, const int32_t *LU, int64_t ld, const int32_t *P,
+                  const int32_t *Q, int64_t r, int32_t *N, int64_t ldn, int path, void *ws, size_t ws_bytes,
+                  ffp_stream_t stream);
+size_t ffp_solve_workspace(int64_t m, int64_t n, int64_t r, int64_t nrhs, uint32_t p, int path);
+int ffp_solve(int64_t m, int64_t n, uint32_t p, const int32_t *LU, int64_t ld, const int32_t *P, const int32_t *Q,
+              int64_t r, int64_t nrhs, const int32_t *B, int64_t ldb, int32_t *X, int64_t ldx, int32_t *consistent,
+              int path, void *ws, size_t ws_bytes, ffp_stream_t stream);
 
 /* --------------------------------------------------------------------------
  * check_range -- the validating call: FFP_E_RANGE if some entry of the m x n

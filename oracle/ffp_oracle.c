@@ -502,3 +502,132 @@ done:
     free(prow); free(pcol); free(orow); free(ocol); free(W);
     return e;
 }
+
+/* ------------------------------------------------------------------ */
+/* Echelon forms and the consumers of a rank profile (Section 1,       */
+/* "Pivoting strategies and rank deficiencies": the pivoting strategies */
+/* that reveal the rank profile reveal the echelon form).  All three    */
+/* come from the textbook Gauss-Jordan elimination below, written out   */
+/* on its own (no use of the PLUQ above).                               */
+/* ------------------------------------------------------------------ */
+
+/* Gauss-Jordan on the m x w matrix W (int64, ld w), pivoting only in the
+ * first n columns: columns are visited left to right; the first row at or
+ * below the current rank with a nonzero in the column is swapped up, scaled
+ * to a unit pivot, and the column is cleared in every other row.  Returns
+ * the rank; piv[t] receives the column of pivot t. */
+static int64_t gauss_jordan(int64_t m, int64_t n, int64_t w, int64_t *W, int64_t P, int32_t *piv) {
+    int64_t r = 0;
+    for (int64_t c = 0; c < n && r < m; c++) {
+        int64_t i0 = -1;
+        for (int64_t i = r; i < m; i++)
+            if (W[i * w + c] != 0) { i0 = i; break; }
+        if (i0 < 0) continue;
+        if (i0 != r)
+            for (int64_t j = 0; j < w; j++) {
+                int64_t t = W[i0 * w + j]; W[i0 * w + j] = W[r * w + j]; W[r * w + j] = t;
+            }
+        const int64_t inv = orc_inv(W[r * w + c], P);
+        for (int64_t j = 0; j < w; j++) W[r * w + j] = mulmod(W[r * w + j], inv, P);
+        const int64_t *rowr = W + r * w;
+#pragma omp parallel for schedule(static) if (m * w > (1 << 16))
+        for (int64_t i = 0; i < m; i++) {
+            if (i == r) continue;
+            int64_t *rowi = W + i * w;
+            const int64_t f = rowi[c];
+            if (f == 0) continue;
+            for (int64_t j = 0; j < w; j++) rowi[j] = md(rowi[j] - mulmod(f, rowr[j], P), P);
+        }
+        piv[r++] = (int32_t)c;
+    }
+    return r;
+}
+
+/* Reduced row echelon form: R (m x n, ld n) receives the RREF of A (rows
+ * r..m-1 zero), pivcols[0..r) its pivot columns (ascending: the column rank
+ * profile).  Pinned in tests by the characterisation of the RREF: R[:,
+ * pivcols] = I, the leading entry of row t in column pivcols[t], and
+ * A = A[:, pivcols] R (the row spaces agree). */
+int orc_rref(int64_t m, int64_t n, uint32_t p, const int32_t *A, int64_t lda, int32_t *R, int32_t *pivcols,
+             int64_t *rank) {
+    int e = check_field(p);
+    if (e) return e;
+    if (m < 0 || n < 0) return ORC_E_ARG;
+    if ((e = check_entries(m, n, A, lda, p))) return e;
+    int64_t *W = (int64_t *)malloc(sizeof(int64_t) * (m * n > 0 ? m * n : 1));
+    if (!W) return ORC_E_NOMEM;
+    for (int64_t i = 0; i < m; i++)
+        for (int64_t j = 0; j < n; j++) W[i * n + j] = A[i * lda + j];
+    *rank = gauss_jordan(m, n, n, W, p, pivcols);
+    for (int64_t i = 0; i < m * n; i++) R[i] = (int32_t)W[i];
+    free(W);
+    return ORC_OK;
+}
+
+/* Right nullspace: N (n x (n - r), ld n - r) with A N = 0, one column per
+ * non-pivot column f_j of the RREF (ascending): N[f_j][j] = 1, zero on the
+ * other non-pivot columns, -R[t][f_j] on pivot column pivcols[t].
+ * Pinned in tests by A N = 0 and N = I on the non-pivot rows (which
+ * determines a basis of the kernel uniquely). */
+int orc_nullspace(int64_t m, int64_t n, uint32_t p, const int32_t *A, int64_t lda, int32_t *N, int64_t *rank) {
+    int e = check_field(p);
+    if (e) return e;
+    if (m < 0 || n < 0) return ORC_E_ARG;
+    int32_t *R = (int32_t *)malloc(sizeof(int32_t) * (m * n > 0 ? m * n : 1));
+    int32_t *pc = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    char *isp = (char *)calloc(n > 0 ? n : 1, 1);
+    if (!R || !pc || !isp) { free(R); free(pc); free(isp); return ORC_E_NOMEM; }
+    int64_t r = 0;
+    e = orc_rref(m, n, p, A, lda, R, pc, &r);
+    if (!e) {
+        const int64_t d = n - r, P = p;
+        for (int64_t t = 0; t < r; t++) isp[pc[t]] = 1;
+        for (int64_t i = 0; i < n * d; i++) N[i] = 0;
+        int64_t j = 0;
+        for (int64_t f = 0; f < n; f++) {
+            if (isp[f]) continue;
+            N[f * d + j] = 1;
+            for (int64_t t = 0; t < r; t++) N[(int64_t)pc[t] * d + j] = (int32_t)md(-(int64_t)R[t * n + f], P);
+            j++;
+        }
+        *rank = r;
+    }
+    free(R); free(pc); free(isp);
+    return e;
+}
+
+/* Linear system A X = B (A m x n, B m x nrhs): Gauss-Jordan on [A | B]
+ * pivoting in A's columns only.  consistent[j] = 1 when column j of B lies
+ * in the column space of A (no nonzero left in rows r.. of the reduced B);
+ * then X[:, j] is the solution that is zero on the non-pivot columns (X[
+ * pivcols[t]][j] = reduced B[t][j]); otherwise X[:, j] = 0.
+ * Pinned in tests by A X = B, X zero off the pivot columns, and
+ * inconsistency exactly when rank([A b]) > rank(A). */
+int orc_solve(int64_t m, int64_t n, uint32_t p, const int32_t *A, int64_t lda, int64_t nrhs, const int32_t *B,
+              int64_t ldb, int32_t *X, int64_t ldx, int32_t *consistent, int64_t *rank) {
+    int e = check_field(p);
+    if (e) return e;
+    if (m < 0 || n < 0 || nrhs < 0) return ORC_E_ARG;
+    if ((e = check_entries(m, n, A, lda, p)) || (e = check_entries(m, nrhs, B, ldb, p))) return e;
+    const int64_t w = n + nrhs;
+    int64_t *W = (int64_t *)malloc(sizeof(int64_t) * (m * w > 0 ? m * w : 1));
+    int32_t *pc = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    if (!W || !pc) { free(W); free(pc); return ORC_E_NOMEM; }
+    for (int64_t i = 0; i < m; i++) {
+        for (int64_t j = 0; j < n; j++) W[i * w + j] = A[i * lda + j];
+        for (int64_t j = 0; j < nrhs; j++) W[i * w + n + j] = B[i * ldb + j];
+    }
+    const int64_t r = gauss_jordan(m, n, w, W, p, pc);
+    for (int64_t j = 0; j < nrhs; j++) {
+        int ok = 1;
+        for (int64_t i = r; i < m; i++)
+            if (W[i * w + n + j] != 0) { ok = 0; break; }
+        consistent[j] = ok;
+        for (int64_t c = 0; c < n; c++) X[c * ldx + j] = 0;
+        if (ok)
+            for (int64_t t = 0; t < r; t++) X[(int64_t)pc[t] * ldx + j] = (int32_t)W[t * w + n + j];
+    }
+    *rank = r;
+    free(W); free(pc);
+    return ORC_OK;
+}

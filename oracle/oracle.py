@@ -76,6 +76,10 @@ def _load():
         lib.orc_order.restype = i64
         lib.orc_pluq.argtypes = [i64, i64, u32, i32p, i64, i32p, i32p,
                                  ctypes.POINTER(i64), i32p, i32p, ctypes.c_int]
+        lib.orc_rref.argtypes = [i64, i64, u32, i32p, i64, i32p, i32p, ctypes.POINTER(i64)]
+        lib.orc_nullspace.argtypes = [i64, i64, u32, i32p, i64, i32p, ctypes.POINTER(i64)]
+        lib.orc_solve.argtypes = [i64, i64, u32, i32p, i64, i64, i32p, i64, i32p, i64, i32p,
+                                  ctypes.POINTER(i64)]
         _lib = lib
     return _lib
 
@@ -196,3 +200,47 @@ def pluq(A, p: int, selfcheck: bool = True) -> PLUQ:
         raise OracleError(e, "pluq")
     r = int(r.value)
     return PLUQ(W, P[:m].copy(), Q[:n].copy(), r, rrp[:r].copy(), crp[:r].copy())
+
+
+def rref(A, p: int):
+    """Reduced row echelon form by Gauss-Jordan (see orc_rref).
+
+    Returns (rank, R, pivcols): R is r x n, pivcols the r pivot columns."""
+    A = _mat(A)
+    m, n = A.shape
+    R = np.zeros((max(m, 1), max(n, 1)), np.int32)
+    pc = np.zeros(max(n, 1), np.int32)
+    r = ctypes.c_int64(0)
+    e = _load().orc_rref(m, n, p, _ptr(A), max(n, 1), _ptr(R), _ptr(pc), ctypes.byref(r))
+    if e:
+        raise OracleError(e, "rref")
+    r = int(r.value)
+    return r, R.reshape(-1)[: m * n].reshape(m, n)[:r].copy(), pc[:r].copy()
+
+
+def nullspace(A, p: int):
+    """Right nullspace basis N (n x (n - r)), identity on the non-pivot rows."""
+    A = _mat(A)
+    m, n = A.shape
+    N = np.zeros(max(n * n, 1), np.int32)
+    r = ctypes.c_int64(0)
+    e = _load().orc_nullspace(m, n, p, _ptr(A), max(n, 1), _ptr(N), ctypes.byref(r))
+    if e:
+        raise OracleError(e, "nullspace")
+    r = int(r.value)
+    return N[: n * (n - r)].reshape(n, n - r).copy()
+
+
+def solve(A, B, p: int):
+    """Solutions of A X = B zero on the non-pivot columns; returns (X, consistent, rank)."""
+    A, B = _mat(A), _mat(B)
+    m, n = A.shape
+    nrhs = B.shape[1]
+    X = np.zeros((max(n, 1), max(nrhs, 1)), np.int32)
+    ok = np.zeros(max(nrhs, 1), np.int32)
+    r = ctypes.c_int64(0)
+    e = _load().orc_solve(m, n, p, _ptr(A), max(n, 1), nrhs, _ptr(B), max(nrhs, 1), _ptr(X), max(nrhs, 1),
+                          _ptr(ok), ctypes.byref(r))
+    if e:
+        raise OracleError(e, "solve")
+    return X[:n, :nrhs].copy(), ok[:nrhs].astype(bool), int(r.value)

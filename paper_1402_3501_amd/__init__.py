@@ -54,6 +54,9 @@ def load():
         "ffp_fgemm": ([i32, i32, i64, i64, i64, u32, u32, vp, i64, vp, i64, u32, vp, i64, i32, vp, sz, vp], i32),
         "ffp_fgemm_noalloc": ([i32, i32, i64, i64, i64, u32, u32, vp, i64, vp, i64, u32, vp, i64, i32, vp], i32),
         "ffp_noalloc_scratch_bytes": ([], sz),
+        "ffp_fgemm_wino_workspace": ([i32, i32, i64, i64, i64, u32, i32, i32], sz),
+        "ffp_fgemm_wino": ([i32, i32, i64, i64, i64, u32, u32, vp, i64, vp, i64, u32, vp, i64, i32, i32, vp, sz, vp],
+                           i32),
         "ffp_ftrsm_workspace": ([i32, i32, i32, i32, i64, i64, u32, i32], sz),
         "ffp_ftrsm": ([i32, i32, i32, i32, i64, i64, u32, u32, vp, i64, vp, i64, i32, vp, sz, vp], i32),
         "ffp_flaswp_workspace": ([i32, i64, i64], sz),
@@ -63,6 +66,12 @@ def load():
         "ffp_lu_nopiv_workspace": ([i64, i64, u32, i32], sz),
         "ffp_lu_nopiv": ([i64, i64, u32, vp, i64, vp, i32, vp, sz, vp], i32),
         "ffp_check_range": ([i64, i64, u32, vp, i64, vp], i32),
+        "ffp_echelon_workspace": ([i32, i64, i64, i64, u32, i32], sz),
+        "ffp_echelon": ([i32, i64, i64, u32, vp, i64, vp, vp, i64, vp, i64, i32, vp, sz, vp], i32),
+        "ffp_nullspace_workspace": ([i32, i64, i64, i64, u32, i32], sz),
+        "ffp_nullspace": ([i32, i64, i64, u32, vp, i64, vp, vp, i64, vp, i64, i32, vp, sz, vp], i32),
+        "ffp_solve_workspace": ([i64, i64, i64, i64, u32, i32], sz),
+        "ffp_solve": ([i64, i64, u32, vp, i64, vp, vp, i64, i64, vp, i64, vp, i64, vp, i32, vp, sz, vp], i32),
         "ffp_pluq_batched_workspace": ([i32, i32, i32, u32, i32], sz),
         "ffp_pluq_batched": ([i32, vp, vp, i32, i32, u32, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, sz, vp], i32),
         "ffp_pluq_batched_tune_workspace": ([i32, i32, i32, i64], sz),
@@ -158,6 +167,29 @@ def fgemm(A, B, C, p: int, alpha: int = 1, beta: int = 0, transA: bool = False, 
     keep, ws = _workspace(need, C.device)
     _check(lib.ffp_fgemm(int(transA), int(transB), m, n, k, p, alpha, a, lda, b, ldb, beta, c, ldc, path,
                          ws, need, _stream(C)), "ffp_fgemm")
+    return C
+
+
+WINO_AUTO = -1
+
+
+def fgemm_wino(A, B, C, p: int, alpha: int = 1, beta: int = 0, transA: bool = False, transB: bool = False,
+               path: int = PATH_AUTO, levels: int = WINO_AUTO):
+    """fgemm through Strassen-Winograd steps (levels; WINO_AUTO = the library's
+    measured choice), in place on C (returns C)."""
+    lib = load()
+    a, lda = _mat(A, "A")
+    b, ldb = _mat(B, "B")
+    c, ldc = _mat(C, "C")
+    m, n = C.shape
+    k = A.shape[0] if transA else A.shape[1]
+    if (A.shape[1] if transA else A.shape[0]) != m or (B.shape[1] if transB else B.shape[0]) != k or \
+            (B.shape[0] if transB else B.shape[1]) != n:
+        raise ValueError("fgemm_wino: shape mismatch")
+    need = lib.ffp_fgemm_wino_workspace(int(transA), int(transB), m, n, k, p, path, levels)
+    keep, ws = _workspace(need, C.device)
+    _check(lib.ffp_fgemm_wino(int(transA), int(transB), m, n, k, p, alpha, a, lda, b, ldb, beta, c, ldc, path,
+                              levels, ws, need, _stream(C)), "ffp_fgemm_wino")
     return C
 
 
@@ -264,6 +296,67 @@ def lu_nopiv(A, p: int, info=None, ws=None, path: int = PATH_AUTO):
 
 def lu_nopiv_workspace(m: int, n: int, p: int, path: int = PATH_AUTO) -> int:
     return int(load().ffp_lu_nopiv_workspace(m, n, p, path))
+
+
+def echelon(res: "PLUQResult", p: int, form: int = 0, path: int = PATH_AUTO):
+    """Reduced row (form 0: r x n) or column (form 1: m x r) echelon form of
+    the matrix factored in ``res`` (output of ``pluq``), as a new tensor."""
+    torch = _torch()
+    lib = load()
+    a, lda = _mat(res.LU, "LU")
+    m, n = res.LU.shape
+    r = res.rank
+    E = torch.empty((r, n) if form == 0 else (m, r), dtype=torch.int32, device=res.LU.device)
+    if r == 0:
+        return E
+    e, lde = _mat(E, "E")
+    need = lib.ffp_echelon_workspace(form, m, n, r, p, path)
+    keep, ws = _workspace(need, E.device)
+    _check(lib.ffp_echelon(form, m, n, p, a, lda, _vec(res.P, "P"), _vec(res.Q, "Q"), r, e, lde, path, ws, need,
+                           _stream(E)), "ffp_echelon")
+    return E
+
+
+def nullspace(res: "PLUQResult", p: int, side: int = 0, path: int = PATH_AUTO):
+    """Right (side 0: A N = 0, n x (n - r)) or left (side 1: N A = 0,
+    (m - r) x m) nullspace basis, identity on the non-pivot columns / rows."""
+    torch = _torch()
+    lib = load()
+    a, lda = _mat(res.LU, "LU")
+    m, n = res.LU.shape
+    r = res.rank
+    shape = (n, n - r) if side == 0 else (m - r, m)
+    N = torch.zeros(shape, dtype=torch.int32, device=res.LU.device)
+    if N.numel() == 0:
+        return N
+    nn, ldn = _mat(N, "N")
+    need = lib.ffp_nullspace_workspace(side, m, n, r, p, path)
+    keep, ws = _workspace(need, N.device)
+    _check(lib.ffp_nullspace(side, m, n, p, a, lda, _vec(res.P, "P"), _vec(res.Q, "Q"), r, nn, ldn, path, ws,
+                             need, _stream(N)), "ffp_nullspace")
+    return N
+
+
+def solve(res: "PLUQResult", B, p: int, path: int = PATH_AUTO):
+    """A X = B from the factorisation in ``res``: returns (X, consistent) with
+    X (n x nrhs) zero off the pivot columns and consistent an int32 flag per
+    column of B."""
+    torch = _torch()
+    lib = load()
+    a, lda = _mat(res.LU, "LU")
+    m, n = res.LU.shape
+    b, ldb = _mat(B, "B")
+    nrhs = B.shape[1]
+    X = torch.zeros((n, nrhs), dtype=torch.int32, device=B.device)
+    ok = torch.zeros(max(nrhs, 1), dtype=torch.int32, device=B.device)
+    if nrhs == 0:
+        return X, ok[:0]
+    x, ldx = _mat(X, "X")
+    need = lib.ffp_solve_workspace(m, n, res.rank, nrhs, p, path)
+    keep, ws = _workspace(need, B.device)
+    _check(lib.ffp_solve(m, n, p, a, lda, _vec(res.P, "P"), _vec(res.Q, "Q"), res.rank, nrhs, b, ldb, x, ldx,
+                         _vec(ok, "consistent"), path, ws, need, _stream(B)), "ffp_solve")
+    return X, ok[:nrhs]
 
 
 def check_range(A, p: int) -> bool:

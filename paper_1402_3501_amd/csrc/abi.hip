@@ -1,6 +1,7 @@
 // Exported C ABI (include/ffpluq.h): argument validation, path selection,
 // workspace accounting, and the host-side permutation helpers.
 #include <cstring>
+#include <functional>
 #include <vector>
 
 #include "ffp_internal.hpp"
@@ -142,6 +143,146 @@ int ffp_fgemm(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t 
     ar.cap = ws_bytes;
     return fgemm_any(eff, F, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ar,
                      (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------ fgemm, Winograd
+static int wino_levels(int levels, int eff, const Field &F, int64_t m, int64_t n, int64_t k) {
+    return levels == FFP_WINO_AUTO ? wino_auto_levels(eff, F, m, n, k) : levels;
+}
+
+size_t ffp_fgemm_wino_workspace(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t p, int path,
+                                int levels) {
+    (void)transA;
+    (void)transB;
+    if (p < 2 || m < 0 || n < 0 || k < 0 || levels < FFP_WINO_AUTO || levels > FFP_WINO_MAX_LEVELS) return 0;
+    Field F(p);
+    const int lv = wino_levels(levels, path, F, m, n, k);
+    return fgemm_wino_ws(path, F, lv, m, n, k) + 256;
+}
+
+int ffp_fgemm_wino(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t p, uint32_t alpha,
+                   const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta, int32_t *C,
+                   int64_t ldc, int path, int levels, void *ws, size_t ws_bytes, ffp_stream_t stream) {
+    int eff = 0;
+    FFP_CHECK(fgemm_validate(transA, transB, m, n, k, p, alpha, A, lda, B, ldb, beta, C, ldc, path, &eff));
+    if (levels < FFP_WINO_AUTO || levels > FFP_WINO_MAX_LEVELS) return -16;
+    if (m == 0 || n == 0) return FFP_OK;
+    const size_t need = ffp_fgemm_wino_workspace(transA, transB, m, n, k, p, path, levels);
+    if (need > 0 && (!ws || ws_bytes < need)) return FFP_E_WORKSPACE;
+    Field F(p);
+    const int lv = wino_levels(levels, path, F, m, n, k);
+    Arena ar;
+    ar.base = (char *)ws;
+    ar.cap = ws_bytes;
+    return fgemm_wino(path, F, lv, transA, transB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ar,
+                      (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------ echelon forms
+// Common checks of the PLUQ-consumer calls: sizes, field, factor pointers and
+// the rank.  Their arguments (m, n, p, LU, ld, P, Q, r) sit at positions
+// off + 1 .. off + 8; the path is argument arg_path.
+static int check_factors(int64_t m, int64_t n, uint32_t p, const int32_t *LU, int64_t ld, const int32_t *P,
+                         const int32_t *Q, int64_t r, int path, int off, int arg_path) {
+    if (m < 0 || m > INT32_MAX) return -(off + 1);
+    if (n < 0 || n > INT32_MAX) return -(off + 2);
+    FFP_CHECK(check_field(p, path, off + 3, arg_path));
+    if (m > 0 && n > 0 && !LU) return -(off + 4);
+    if (ld < (n > 1 ? n : 1)) return -(off + 5);
+    if (m > 0 && !P) return -(off + 6);
+    if (n > 0 && !Q) return -(off + 7);
+    if (r < 0 || r > (m < n ? m : n)) return -(off + 8);
+    return FFP_OK;
+}
+
+static size_t count_ws(const std::function<int(Arena &)> &f) {
+    Arena ar;
+    ar.counting = true;
+    f(ar);
+    return ar.peak + 512;
+}
+
+size_t ffp_echelon_workspace(int form, int64_t m, int64_t n, int64_t r, uint32_t p, int path) {
+    if (p < 2 || m < 0 || n < 0 || r < 0 || r > (m < n ? m : n) || (form != 0 && form != 1)) return 0;
+    Field F(p);
+    const int32_t dummy = 0;
+    return count_ws([&](Arena &ar) {
+        return echelon_run(form, path, F, m, n, &dummy, n > 1 ? n : 1, &dummy, &dummy, r, nullptr, 1, ar, nullptr);
+    });
+}
+
+int ffp_echelon(int form, int64_t m, int64_t n, uint32_t p, const int32_t *LU, int64_t ld, const int32_t *P,
+                const int32_t *Q, int64_t r, int32_t *E, int64_t lde, int path, void *ws, size_t ws_bytes,
+                ffp_stream_t stream) {
+    if (form != 0 && form != 1) return -1;
+    FFP_CHECK(check_factors(m, n, p, LU, ld, P, Q, r, path, 1, 12));
+    if (r == 0) return FFP_OK;
+    if (!E) return -10;
+    if (lde < (form == 0 ? n : r)) return -11;
+    const size_t need = ffp_echelon_workspace(form, m, n, r, p, path);
+    if (!ws || ws_bytes < need) return FFP_E_WORKSPACE;
+    Field F(p);
+    Arena ar;
+    ar.base = (char *)ws;
+    ar.cap = ws_bytes;
+    return echelon_run(form, path, F, m, n, LU, ld, P, Q, r, E, lde, ar, (hipStream_t)stream);
+}
+
+size_t ffp_nullspace_workspace(int side, int64_t m, int64_t n, int64_t r, uint32_t p, int path) {
+    if (p < 2 || m < 0 || n < 0 || r < 0 || r > (m < n ? m : n) || (side != 0 && side != 1)) return 0;
+    Field F(p);
+    const int32_t dummy = 0;
+    return count_ws([&](Arena &ar) {
+        return nullspace_run(side, path, F, m, n, &dummy, n > 1 ? n : 1, &dummy, &dummy, r, nullptr, 1, ar, nullptr);
+    });
+}
+
+int ffp_nullspace(int side, int64_t m, int64_t n, uint32_t p, const int32_t *LU, int64_t ld, const int32_t *P,
+                  const int32_t *Q, int64_t r, int32_t *N, int64_t ldn, int path, void *ws, size_t ws_bytes,
+                  ffp_stream_t stream) {
+    if (side != 0 && side != 1) return -1;
+    FFP_CHECK(check_factors(m, n, p, LU, ld, P, Q, r, path, 1, 12));
+    const int64_t rows = side == 0 ? n : m - r, cols = side == 0 ? n - r : m;
+    if (rows == 0 || cols == 0) return FFP_OK;
+    if (!N) return -10;
+    if (ldn < cols) return -11;
+    const size_t need = ffp_nullspace_workspace(side, m, n, r, p, path);
+    if (!ws || ws_bytes < need) return FFP_E_WORKSPACE;
+    Field F(p);
+    Arena ar;
+    ar.base = (char *)ws;
+    ar.cap = ws_bytes;
+    return nullspace_run(side, path, F, m, n, LU, ld, P, Q, r, N, ldn, ar, (hipStream_t)stream);
+}
+
+size_t ffp_solve_workspace(int64_t m, int64_t n, int64_t r, int64_t nrhs, uint32_t p, int path) {
+    if (p < 2 || m < 0 || n < 0 || r < 0 || r > (m < n ? m : n) || nrhs < 0) return 0;
+    Field F(p);
+    const int32_t dummy = 0;
+    return count_ws([&](Arena &ar) {
+        return solve_run(path, F, m, n, &dummy, n > 1 ? n : 1, &dummy, &dummy, r, nrhs, &dummy, nrhs > 1 ? nrhs : 1,
+                         nullptr, 1, nullptr, ar, nullptr);
+    });
+}
+
+int ffp_solve(int64_t m, int64_t n, uint32_t p, const int32_t *LU, int64_t ld, const int32_t *P, const int32_t *Q,
+              int64_t r, int64_t nrhs, const int32_t *B, int64_t ldb, int32_t *X, int64_t ldx, int32_t *consistent,
+              int path, void *ws, size_t ws_bytes, ffp_stream_t stream) {
+    FFP_CHECK(check_factors(m, n, p, LU, ld, P, Q, r, path, 0, 15));
+    if (nrhs < 0) return -9;
+    if (nrhs == 0) return FFP_OK;
+    if (m > 0 && !B) return -10;
+    if (ldb < nrhs) return -11;
+    if (n > 0 && !X) return -12;
+    if (ldx < nrhs) return -13;
+    if (!consistent) return -14;
+    const size_t need = ffp_solve_workspace(m, n, r, nrhs, p, path);
+    if (!ws || ws_bytes < need) return FFP_E_WORKSPACE;
+    Field F(p);
+    Arena ar;
+    ar.base = (char *)ws;
+    ar.cap = ws_bytes;
+    return solve_run(path, F, m, n, LU, ld, P, Q, r, nrhs, B, ldb, X, ldx, consistent, ar, (hipStream_t)stream);
 }
 
 // ------------------------------------------------------------------ ftrsm

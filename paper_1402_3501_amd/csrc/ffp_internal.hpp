@@ -117,6 +117,28 @@ int fgemm_validate(int transA, int transB, int64_t m, int64_t n, int64_t k, uint
                    const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta, const int32_t *C,
                    int64_t ldc, int path, int *eff);
 
+// Strassen-Winograd levels over fgemm_any (winograd.hip); levels = 0 is the
+// plain product.  Block products below kWinoMinDim* in some dimension are
+// not split further by the automatic level choice.
+constexpr int64_t kWinoMinDimF64 = 4096;
+constexpr int64_t kWinoMinDimI8 = 4096;
+size_t fgemm_wino_ws(int path, const Field &F, int levels, int64_t m, int64_t n, int64_t k);
+int fgemm_wino(int path, const Field &F, int levels, int ta, int tb, int64_t m, int64_t n, int64_t k,
+               uint32_t alpha, const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta,
+               int32_t *C, int64_t ldc, Arena &ws, hipStream_t s);
+int wino_auto_levels(int path, const Field &F, int64_t m, int64_t n, int64_t k);
+
+// consumers of a PLUQ (echelon.hip): reduced row (form 0, r x n) or column
+// (form 1, m x r) echelon form, right (side 0) or left (side 1) nullspace,
+// and A X = B with per-column consistency flags; workspace by counting mode
+int echelon_run(int form, int path, const Field &F, int64_t m, int64_t n, const int32_t *LU, int64_t ld,
+                const int32_t *P, const int32_t *Q, int64_t r, int32_t *E, int64_t lde, Arena &ws, hipStream_t s);
+int nullspace_run(int side, int path, const Field &F, int64_t m, int64_t n, const int32_t *LU, int64_t ld,
+                  const int32_t *P, const int32_t *Q, int64_t r, int32_t *N, int64_t ldn, Arena &ws, hipStream_t s);
+int solve_run(int path, const Field &F, int64_t m, int64_t n, const int32_t *LU, int64_t ld, const int32_t *P,
+              const int32_t *Q, int64_t r, int64_t nrhs, const int32_t *B, int64_t ldb, int32_t *X, int64_t ldx,
+              int32_t *ok, Arena &ws, hipStream_t s);
+
 // triangular solve (recursive onto fgemm_any); alpha applied first
 int ftrsm_run(int path, const Field &F, int side, int uplo, int trans, int diag, int64_t m,
               int64_t n, uint32_t alpha, const int32_t *T, int64_t ldt, int32_t *B, int64_t ldb,
