@@ -229,6 +229,55 @@ int ffp_lu_nopiv(int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int3
                  void *ws, size_t ws_bytes, ffp_stream_t stream);
 
 /* --------------------------------------------------------------------------
+ * pluq_slab -- the slab-recursive PLUQ of Section 4.1 ("Pivoting
+ * strategies"): the row-major pivot search (rows in order, a row with no
+ * nonzero left skipped, otherwise its leftmost remaining nonzero is the next
+ * pivot) as a recursion on halves of the rows.  Same arguments, outputs and
+ * layout as ffp_pluq, except the pivot order: pivots in increasing row
+ * order, so P[0:r] is the row rank profile itself; the pivot pairs are the
+ * same rank profile matrix, rrp / crp the same profiles, and non-pivot rows
+ * and columns ascend.  At most FFP_SLAB_MAX_COLS columns (argument 2 else).
+ * Synchronises `stream` once per slab of 32 rows (rank read-back).
+ * Workspace: ffp_pluq_slab_workspace bytes.
+ * -------------------------------------------------------------------------- */
+#define FFP_SLAB_MAX_COLS 65536
+size_t ffp_pluq_slab_workspace(int64_t m, int64_t n, uint32_t p, int path);
+int ffp_pluq_slab(int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int32_t *P, int32_t *Q, int64_t *rank_dev,
+                  int64_t *rank_host, int32_t *rrp, int32_t *crp, int path, void *ws, size_t ws_bytes,
+                  ffp_stream_t stream);
+
+/* --------------------------------------------------------------------------
+ * lu_tiled -- the tile-iterative block LU of Section 3.1 (Table 1) in one of
+ * its three orders, for an input of generic rank profile (the assumption of
+ * Section 3): variant FFP_LU_RIGHT (right-looking), FFP_LU_CROUT or
+ * FFP_LU_LEFT (left-looking), with k x k diagonal tiles (k >= 1; the last one
+ * may be smaller).  The result, when every pivot is nonzero, is the unique LU
+ * without pivoting, bit-identical to what ffp_pluq returns for such an input
+ * (P = Q = identity).  Asynchronous (no host synchronisation):
+ *   info_dev: device int32 receiving 0, or 1 + the diagonal index of the
+ *     first zero pivot (A is then left in an unspecified state).
+ * Workspace: ffp_lu_tiled_workspace bytes.
+ *
+ * reduction_count -- host only, no device: the number of modular reductions
+ * the model of Section 3.1 charges an n x n factorisation (a product m x k
+ * by k x n: m n; a unit triangular solve m x m with n right-hand sides:
+ * (m - 1) n; a non-unit one: (2 m - 1) n; a k x k base case: 3/2 k^2 -
+ * 7/2 k + 3, the unblocked Crout count).  For FFP_LU_RIGHT / CROUT / LEFT it
+ * runs the loops of ffp_lu_tiled with tile k without launching anything;
+ * FFP_LU_TILE_RECURSIVE and FFP_LU_SLAB_RECURSIVE are the halving recursions
+ * of the four-quadrant and the row-slab algorithms (k ignored).
+ * -------------------------------------------------------------------------- */
+#define FFP_LU_RIGHT 0
+#define FFP_LU_CROUT 1
+#define FFP_LU_LEFT 2
+#define FFP_LU_TILE_RECURSIVE 3
+#define FFP_LU_SLAB_RECURSIVE 4
+size_t ffp_lu_tiled_workspace(int variant, int64_t m, int64_t n, int64_t k, uint32_t p, int path);
+int ffp_lu_tiled(int variant, int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int64_t k, int32_t *info_dev,
+                 int path, void *ws, size_t ws_bytes, ffp_stream_t stream);
+int ffp_reduction_count(int algorithm, int64_t n, int64_t k, double *count);
+
+/* --------------------------------------------------------------------------
  * Consumers of the rank profile (Section 1, "Pivoting strategies and rank
  * deficiencies": the pivoting that reveals the rank profile reveals the
  * echelon form).  They take the output of ffp_pluq as it stands: LU (m x n,

@@ -631,3 +631,51 @@ int orc_solve(int64_t m, int64_t n, uint32_t p, const int32_t *A, int64_t lda, i
     free(W); free(pc);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* PLUQ in the order of the row-major search itself (Section 4.1: the   */
+/* pivoting of the slab algorithms, rows visited in order, a row with   */
+/* no nonzero left skipped): pivots in increasing row order, each       */
+/* paired with the leftmost remaining nonzero column of its row;        */
+/* non-pivot rows and columns ascending.  This is exactly pass 1 above, */
+/* gathered into P, Q order: A[P[i]][Q[j]] = sum_t L[i][t] U[t][j].     */
+/* Pinned in tests: the pivots are R_A (minor enumeration, as pass 1),  */
+/* the pivot rows ascend, A == PLUQ exactly, triangular structure.      */
+/* ------------------------------------------------------------------ */
+int orc_pluq_rowmajor(int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int32_t *Pout, int32_t *Qout,
+                      int64_t *rank, int32_t *rrp, int32_t *crp) {
+    int e = check_field(p);
+    if (e) return e;
+    if (m < 0 || n < 0 || lda < (n > 0 ? n : 0)) return ORC_E_ARG;
+    const int64_t mn = m < n ? m : n;
+    int32_t *prow = (int32_t *)malloc(sizeof(int32_t) * (mn ? mn : 1));
+    int32_t *pcol = (int32_t *)malloc(sizeof(int32_t) * (mn ? mn : 1));
+    int64_t *W = (int64_t *)malloc(sizeof(int64_t) * (m > 0 && n > 0 ? m * n : 1));
+    char *rp = (char *)calloc(m ? m : 1, 1), *cp = (char *)calloc(n ? n : 1, 1);
+    if (!prow || !pcol || !W || !rp || !cp) { e = ORC_E_NOMEM; goto done; }
+    int64_t r = 0;
+    e = orc_pivots(m, n, p, A, lda, prow, pcol, &r, W);
+    if (e) goto done;
+    for (int64_t t = 0; t < r; t++) {
+        Pout[t] = prow[t]; Qout[t] = pcol[t];
+        rp[prow[t]] = 1; cp[pcol[t]] = 1;
+    }
+    {
+        int64_t k = r;
+        for (int64_t i = 0; i < m; i++) if (!rp[i]) Pout[k++] = (int32_t)i;
+        k = r;
+        for (int64_t j = 0; j < n; j++) if (!cp[j]) Qout[k++] = (int32_t)j;
+    }
+    for (int64_t i = 0; i < m; i++)
+        for (int64_t j = 0; j < n; j++) A[i * lda + j] = (int32_t)W[(int64_t)Pout[i] * n + Qout[j]];
+    *rank = r;
+    {
+        int64_t k = 0;
+        for (int64_t i = 0; i < m; i++) if (rp[i]) rrp[k++] = (int32_t)i;
+        k = 0;
+        for (int64_t j = 0; j < n; j++) if (cp[j]) crp[k++] = (int32_t)j;
+    }
+done:
+    free(prow); free(pcol); free(W); free(rp); free(cp);
+    return e;
+}

@@ -76,6 +76,7 @@ def _load():
         lib.orc_order.restype = i64
         lib.orc_pluq.argtypes = [i64, i64, u32, i32p, i64, i32p, i32p,
                                  ctypes.POINTER(i64), i32p, i32p, ctypes.c_int]
+        lib.orc_pluq_rowmajor.argtypes = [i64, i64, u32, i32p, i64, i32p, i32p, ctypes.POINTER(i64), i32p, i32p]
         lib.orc_rref.argtypes = [i64, i64, u32, i32p, i64, i32p, i32p, ctypes.POINTER(i64)]
         lib.orc_nullspace.argtypes = [i64, i64, u32, i32p, i64, i32p, ctypes.POINTER(i64)]
         lib.orc_solve.argtypes = [i64, i64, u32, i32p, i64, i64, i32p, i64, i32p, i64, i32p,
@@ -198,6 +199,25 @@ def pluq(A, p: int, selfcheck: bool = True) -> PLUQ:
                          _ptr(rrp), _ptr(crp), int(bool(selfcheck)))
     if e:
         raise OracleError(e, "pluq")
+    r = int(r.value)
+    return PLUQ(W, P[:m].copy(), Q[:n].copy(), r, rrp[:r].copy(), crp[:r].copy())
+
+
+def pluq_rowmajor(A, p: int) -> PLUQ:
+    """PLUQ in the order of the row-major search (see orc_pluq_rowmajor):
+    pivots in increasing row order, the output of the slab algorithms."""
+    W = _mat(A).copy()
+    m, n = W.shape
+    P = np.zeros(max(m, 1), np.int32)
+    Q = np.zeros(max(n, 1), np.int32)
+    k = max(min(m, n), 1)
+    rrp = np.zeros(k, np.int32)
+    crp = np.zeros(k, np.int32)
+    r = ctypes.c_int64(0)
+    e = _load().orc_pluq_rowmajor(m, n, p, _ptr(W), max(n, 1), _ptr(P), _ptr(Q), ctypes.byref(r),
+                                  _ptr(rrp), _ptr(crp))
+    if e:
+        raise OracleError(e, "pluq_rowmajor")
     r = int(r.value)
     return PLUQ(W, P[:m].copy(), Q[:n].copy(), r, rrp[:r].copy(), crp[:r].copy())
 

@@ -63,9 +63,14 @@ def load():
         "ffp_flaswp": ([i32, i64, i64, vp, i64, vp, i32, vp, sz, vp], i32),
         "ffp_pluq_workspace": ([i64, i64, u32, i32], sz),
         "ffp_pluq": ([i64, i64, u32, vp, i64, vp, vp, vp, ctypes.POINTER(i64), vp, vp, i32, vp, sz, vp], i32),
+        "ffp_pluq_slab_workspace": ([i64, i64, u32, i32], sz),
+        "ffp_pluq_slab": ([i64, i64, u32, vp, i64, vp, vp, vp, ctypes.POINTER(i64), vp, vp, i32, vp, sz, vp], i32),
         "ffp_lu_nopiv_workspace": ([i64, i64, u32, i32], sz),
         "ffp_lu_nopiv": ([i64, i64, u32, vp, i64, vp, i32, vp, sz, vp], i32),
         "ffp_check_range": ([i64, i64, u32, vp, i64, vp], i32),
+        "ffp_lu_tiled_workspace": ([i32, i64, i64, i64, u32, i32], sz),
+        "ffp_lu_tiled": ([i32, i64, i64, u32, vp, i64, i64, vp, i32, vp, sz, vp], i32),
+        "ffp_reduction_count": ([i32, i64, i64, ctypes.POINTER(ctypes.c_double)], i32),
         "ffp_echelon_workspace": ([i32, i64, i64, i64, u32, i32], sz),
         "ffp_echelon": ([i32, i64, i64, u32, vp, i64, vp, vp, i64, vp, i64, i32, vp, sz, vp], i32),
         "ffp_nullspace_workspace": ([i32, i64, i64, i64, u32, i32], sz),
@@ -256,6 +261,27 @@ def pluq(A, p: int, path: int = PATH_AUTO) -> PLUQResult:
     return PLUQResult(A, P[:m], Q[:n], r, rrp[:r], crp[:r])
 
 
+def pluq_slab(A, p: int, path: int = PATH_AUTO) -> PLUQResult:
+    """Slab-recursive PLUQ of A in place (pivots in row order).  Synchronises."""
+    torch = _torch()
+    lib = load()
+    a, lda = _mat(A, "A")
+    m, n = A.shape
+    dev = A.device
+    P = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    Q = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    k = max(min(m, n), 1)
+    rrp = torch.empty(k, dtype=torch.int32, device=dev)
+    crp = torch.empty(k, dtype=torch.int32, device=dev)
+    need = lib.ffp_pluq_slab_workspace(m, n, p, path)
+    keep, ws = _workspace(need, dev)
+    r = ctypes.c_int64(-1)
+    _check(lib.ffp_pluq_slab(m, n, p, a, lda, _vec(P, "P"), _vec(Q, "Q"), None, ctypes.byref(r), _vec(rrp, "rrp"),
+                             _vec(crp, "crp"), path, ws, need, _stream(A)), "ffp_pluq_slab")
+    r = int(r.value)
+    return PLUQResult(A, P[:m], Q[:n], r, rrp[:r], crp[:r])
+
+
 def pluq_workspace(m: int, n: int, p: int, path: int = PATH_AUTO) -> int:
     return int(load().ffp_pluq_workspace(m, n, p, path))
 
@@ -296,6 +322,41 @@ def lu_nopiv(A, p: int, info=None, ws=None, path: int = PATH_AUTO):
 
 def lu_nopiv_workspace(m: int, n: int, p: int, path: int = PATH_AUTO) -> int:
     return int(load().ffp_lu_nopiv_workspace(m, n, p, path))
+
+
+LU_RIGHT, LU_CROUT, LU_LEFT, LU_TILE_RECURSIVE, LU_SLAB_RECURSIVE = 0, 1, 2, 3, 4
+
+
+def lu_tiled(A, p: int, variant: int, k: int, info=None, ws=None, path: int = PATH_AUTO):
+    """Tile-iterative LU in place (right-looking, Crout or left-looking, tile
+    k) for an input of generic rank profile; returns the device int32 info
+    (0, or 1 + the index of the first zero pivot).  No host synchronisation."""
+    torch = _torch()
+    lib = load()
+    a, lda = _mat(A, "A")
+    m, n = A.shape
+    if info is None:
+        info = torch.empty(1, dtype=torch.int32, device=A.device)
+    need = lib.ffp_lu_tiled_workspace(variant, m, n, k, p, path)
+    if ws is None:
+        keep, wsp = _workspace(need, A.device)
+        wsz = need
+    else:
+        keep, wsp, wsz = ws, ctypes.c_void_p(ws.data_ptr()), ws.numel()
+    _check(lib.ffp_lu_tiled(variant, m, n, p, a, lda, k, _vec(info, "info"), path, wsp, wsz, _stream(A)),
+           "ffp_lu_tiled")
+    return info
+
+
+def lu_tiled_workspace(variant: int, m: int, n: int, k: int, p: int, path: int = PATH_AUTO) -> int:
+    return int(load().ffp_lu_tiled_workspace(variant, m, n, k, p, path))
+
+
+def reduction_count(algorithm: int, n: int, k: int = 1) -> float:
+    """Modular reductions the model of Section 3.1 charges an n x n LU (host only)."""
+    c = ctypes.c_double(0.0)
+    _check(load().ffp_reduction_count(algorithm, n, k, ctypes.byref(c)), "ffp_reduction_count")
+    return c.value
 
 
 def echelon(res: "PLUQResult", p: int, form: int = 0, path: int = PATH_AUTO):

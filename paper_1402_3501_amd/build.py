@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libffpluq.so")
-SOURCES = ["core.hip", "fgemm_f64.hip", "fgemm_i8.hip", "ftrsm.hip", "pluq.hip", "leaf64.hip", "batched.hip", "abi.hip", "noalloc.hip", "winograd.hip", "echelon.hip"]
+SOURCES = ["core.hip", "fgemm_f64.hip", "fgemm_i8.hip", "ftrsm.hip", "pluq.hip", "leaf64.hip", "batched.hip", "abi.hip", "noalloc.hip", "winograd.hip", "echelon.hip", "tiled.hip", "slab.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

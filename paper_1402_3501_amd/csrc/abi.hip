@@ -178,6 +178,41 @@ int ffp_fgemm_wino(int transA, int transB, int64_t m, int64_t n, int64_t k, uint
                       (hipStream_t)stream);
 }
 
+// ------------------------------------------------------------------ tile-iterative LU
+size_t ffp_lu_tiled_workspace(int variant, int64_t m, int64_t n, int64_t k, uint32_t p, int path) {
+    if (p < 2 || m < 0 || n < 0 || k < 1 || variant < FFP_LU_RIGHT || variant > FFP_LU_LEFT) return 0;
+    Field F(p);
+    return lu_tiled_ws(variant, pluq_path(path, p, m, n), F, m, n, k);
+}
+
+int ffp_lu_tiled(int variant, int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int64_t k, int32_t *info_dev,
+                 int path, void *ws, size_t ws_bytes, ffp_stream_t stream) {
+    if (variant < FFP_LU_RIGHT || variant > FFP_LU_LEFT) return -1;
+    if (m < 0 || m > INT32_MAX) return -2;
+    if (n < 0 || n > INT32_MAX) return -3;
+    FFP_CHECK(check_field(p, path, 4, 9));
+    if (m > 0 && n > 0 && !A) return -5;
+    if (lda < (n > 1 ? n : 1)) return -6;
+    if (k < 1) return -7;
+    if (!info_dev) return -8;
+    const size_t need = ffp_lu_tiled_workspace(variant, m, n, k, p, path);
+    if (!ws || ws_bytes < need) return FFP_E_WORKSPACE;
+    Field F(p);
+    Arena ar;
+    ar.base = (char *)ws;
+    ar.cap = ws_bytes;
+    return lu_tiled_run(variant, pluq_path(path, p, m, n), F, m, n, k, A, lda, (int *)info_dev, ar,
+                        (hipStream_t)stream, nullptr);
+}
+
+int ffp_reduction_count(int algorithm, int64_t n, int64_t k, double *count) {
+    if (algorithm < FFP_LU_RIGHT || algorithm > FFP_LU_SLAB_RECURSIVE) return -1;
+    if (n < 0) return -2;
+    if (k < 1 && algorithm <= FFP_LU_LEFT) return -3;
+    if (!count) return -4;
+    return reduction_count(algorithm, n, k, count);
+}
+
 // ------------------------------------------------------------------ echelon forms
 // Common checks of the PLUQ-consumer calls: sizes, field, factor pointers and
 // the rank.  Their arguments (m, n, p, LU, ld, P, Q, r) sit at positions
@@ -393,6 +428,46 @@ int ffp_pluq(int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int32_t 
     int64_t r = 0;
     // with FFP_PATH_AUTO every product inside the factorisation picks its own path
     FFP_CHECK(pluq_run(path, F, m, n, A, lda, P, Q, &r, ar, s));
+    if (rank_dev) {
+        hipLaunchKernelGGL(k_set64, dim3(1), dim3(1), 0, s, rank_dev, r);
+        FFP_HIP_CHECK(hipGetLastError());
+    }
+    FFP_CHECK(rank_profiles(m, n, P, Q, r, rrp, crp, ar, s));
+    if (rank_host) {
+        FFP_HIP_CHECK(hipStreamSynchronize(s));
+        *rank_host = r;
+    }
+    return FFP_OK;
+}
+
+// ------------------------------------------------------------------ slab-recursive PLUQ
+size_t ffp_pluq_slab_workspace(int64_t m, int64_t n, uint32_t p, int path) {
+    if (p < 2 || m < 0 || n < 0) return 0;
+    Field F(p);
+    const int eff = pluq_path(path, p, m, n);
+    return pluq_slab_ws(m, n, F, eff == FFP_PATH_INT8 && int8_limbs(p) > 0 ? FFP_PATH_INT8 : FFP_PATH_FP64) +
+           (size_t)(m + n) * 4 + 4096;
+}
+
+int ffp_pluq_slab(int64_t m, int64_t n, uint32_t p, int32_t *A, int64_t lda, int32_t *P, int32_t *Q, int64_t *rank_dev,
+                  int64_t *rank_host, int32_t *rrp, int32_t *crp, int path, void *ws, size_t ws_bytes,
+                  ffp_stream_t stream) {
+    if (m < 0 || m > INT32_MAX) return -1;
+    if (n < 0 || n > FFP_SLAB_MAX_COLS) return -2;
+    FFP_CHECK(check_field(p, path, 3, 12));
+    if (m > 0 && n > 0 && !A) return -4;
+    if (lda < (n > 1 ? n : 1)) return -5;
+    if (m > 0 && !P) return -6;
+    if (n > 0 && !Q) return -7;
+    const size_t need = ffp_pluq_slab_workspace(m, n, p, path);
+    if (!ws || ws_bytes < need) return FFP_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    Field F(p);
+    Arena ar;
+    ar.base = (char *)ws;
+    ar.cap = ws_bytes;
+    int64_t r = 0;
+    FFP_CHECK(pluq_slab_run(path, F, m, n, A, lda, P, Q, &r, ar, s));
     if (rank_dev) {
         hipLaunchKernelGGL(k_set64, dim3(1), dim3(1), 0, s, rank_dev, r);
         FFP_HIP_CHECK(hipGetLastError());

@@ -209,8 +209,28 @@ size_t pluq_ws(int64_t m, int64_t n, const Field &F, int path);
 // or 1 + the diagonal index of the first zero pivot
 int lu_nopiv_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int *info, Arena &ws,
                  hipStream_t s);
+// generic-rank-profile LU of one block at diagonal offset d0, sharing the
+// zero-pivot flag *info with other blocks (set only if still clear)
+int lu_block_generic(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int *info, int64_t d0,
+                     Arena &ws, hipStream_t s);
+// tile-iterative LU (tiled.hip): variant FFP_LU_RIGHT / CROUT / LEFT, tile k;
+// *reductions = the modular-reduction count of the model of Section 3.1
+int lu_tiled_run(int variant, int path, const Field &F, int64_t m, int64_t n, int64_t k, int32_t *A, int64_t lda,
+                 int *info, Arena &ws, hipStream_t s, double *reductions);
+size_t lu_tiled_ws(int variant, int path, const Field &F, int64_t m, int64_t n, int64_t k);
+int reduction_count(int algorithm, int64_t n, int64_t k, double *count);
 // *ok = every entry of the block lies in [0, p) (synchronises s)
 int check_range_run(int64_t m, int64_t n, uint32_t p, const int32_t *A, int64_t lda, hipStream_t s, bool *ok);
+// slab-recursive PLUQ (slab.hip): pivots in the order of the row-major search
+size_t pluq_slab_ws(int64_t m, int64_t n, const Field &F, int path);
+int pluq_slab_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
+                  int64_t *r, Arena &ws, hipStream_t s);
+// a pinned, device-visible host word for one rank / flag read-back (pooled)
+struct RankWord {
+    int64_t *host = nullptr, *dev = nullptr;
+};
+int rank_word_get(RankWord *w);
+void rank_word_put(const RankWord &w);
 // sorted rank profiles from P[0:r] (device); r is a host value
 int rank_profiles(int64_t m, int64_t n, const int32_t *P, const int32_t *Q, int64_t r,
                   int32_t *rrp, int32_t *crp, Arena &ws, hipStream_t s);

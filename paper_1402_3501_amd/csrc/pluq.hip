@@ -448,16 +448,14 @@ static int iota(int32_t *v, int64_t n, hipStream_t s) {
 }
 
 // ===================================================================== host recursion
-namespace {
-std::mutex g_pin_mu;
 // Host words the leaves of the general recursion write their rank into
 // directly (pinned, coherent, device-visible): the host reads a rank after
 // one stream synchronisation, with no copy on the stream.  One word per
 // concurrent call, taken from a pool and kept for the life of the process.
-struct RankWord {
-    int64_t *host = nullptr, *dev = nullptr;
-};
+namespace {
+std::mutex g_pin_mu;
 std::vector<RankWord> g_rank_pool;
+}  // namespace
 
 int rank_word_get(RankWord *w) {
     std::lock_guard<std::mutex> g(g_pin_mu);
@@ -474,6 +472,8 @@ void rank_word_put(const RankWord &w) {
     std::lock_guard<std::mutex> g(g_pin_mu);
     g_rank_pool.push_back(w);
 }
+
+namespace {
 
 // A second stream (one per device, default priority) for the triangular
 // solve E = C1 U1^-1 and the product G -= E V1, which are independent of
@@ -955,6 +955,25 @@ int lu_nopiv_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int
     Ctx c{path, &F, &ws, s, nullptr, nullptr, info};
     c.gen_k = 0;
     FFP_CHECK(lu_generic(c, m, n, A, lda, info, Li, Ui, 0));
+    ws.release(mk);
+    return FFP_OK;
+}
+
+// The generic-rank-profile LU of one block at diagonal offset d0 (the base
+// case of the tile-iterative variants): a zero pivot sets *info = 1 + its
+// index on the whole diagonal unless *info is already set (later leaves then
+// return at once).  Asynchronous.
+int lu_block_generic(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int *info, int64_t d0,
+                     Arena &ws, hipStream_t s) {
+    if (m == 0 || n == 0) return FFP_OK;
+    const size_t mk = ws.mark();
+    const size_t nblk = (size_t)(((m < n ? m : n) + 63) / 64);
+    double *Li = (double *)ws.take(nblk * kBlk * sizeof(double));
+    double *Ui = (double *)ws.take(nblk * kBlk * sizeof(double));
+    if (!Li || !Ui) return FFP_E_WORKSPACE;
+    Ctx c{path, &F, &ws, s, nullptr, nullptr, info};
+    c.gen_k = 0;
+    FFP_CHECK(lu_generic(c, m, n, A, lda, info, Li, Ui, d0));
     ws.release(mk);
     return FFP_OK;
 }
