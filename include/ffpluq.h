@@ -358,7 +358,11 @@ int ffp_pluq_batched(int32_t batch, const int32_t *m_arr, const int32_t *n_arr, 
  *   shape_out: host int receiving the chosen shape index (may be NULL);
  *   ms_out: host float[FFP_BATCH_SHAPES] receiving each shape's time (may be NULL).
  * -------------------------------------------------------------------------- */
-#define FFP_BATCH_SHAPES 2
+#define FFP_BATCH_SHAPES 4
+/* Record launch shape `shape` (0 .. FFP_BATCH_SHAPES - 1) for batches with
+ * this (batch, max_m, max_n) on the current device, as the tuner does:
+ * for callers that know the best shape already (e.g. from an earlier run). */
+int ffp_pluq_batched_set_shape(int32_t batch, int32_t max_m, int32_t max_n, int shape);
 size_t ffp_pluq_batched_tune_workspace(int32_t batch, int32_t max_m, int32_t max_n, int64_t a_elems);
 int ffp_pluq_batched_tune(int32_t batch, const int32_t *m_arr, const int32_t *n_arr, int32_t max_m,
                           int32_t max_n, uint32_t p, int32_t *A_packed, int64_t a_elems, const int64_t *A_off,

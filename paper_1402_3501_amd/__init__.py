@@ -21,7 +21,7 @@ PATH_AUTO, PATH_FP64, PATH_INT8 = 0, 1, 2
 P_MAX_FP64 = 94906249
 P_MAX_INT8 = 16711421
 BATCH_MAX_DIM = 1024
-BATCH_SHAPES = 2  # launch shapes the batched autotuner chooses from
+BATCH_SHAPES = 4  # launch shapes the batched autotuner chooses from
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libffpluq.so")
@@ -80,6 +80,7 @@ def load():
         "ffp_pluq_batched_workspace": ([i32, i32, i32, u32, i32], sz),
         "ffp_pluq_batched": ([i32, vp, vp, i32, i32, u32, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, vp, sz, vp], i32),
         "ffp_pluq_batched_tune_workspace": ([i32, i32, i32, i64], sz),
+        "ffp_pluq_batched_set_shape": ([i32, i32, i32, i32], i32),
         "ffp_pluq_batched_tune": ([i32, vp, vp, i32, i32, u32, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, i32,
                                    ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float), vp, sz, vp], i32),
         "ffp_perm_to_swaps": ([i64, vp, vp], i32),
@@ -513,6 +514,11 @@ def pluq_batched_tune(ms, ns, A_packed, A_off, p: int, path: int = PATH_AUTO):
                                      _vec(crp, "crp"), path, ctypes.byref(shape), times, ws, need,
                                      _stream(A_packed)), "ffp_pluq_batched_tune")
     return BatchedResult(P, Q, rank[:batch], rrp, crp), shape.value, [times[i] for i in range(BATCH_SHAPES)]
+
+
+def pluq_batched_set_shape(batch: int, max_m: int, max_n: int, shape: int) -> None:
+    """Use launch shape ``shape`` for later batched calls of this description."""
+    _check(load().ffp_pluq_batched_set_shape(batch, max_m, max_n, shape), "ffp_pluq_batched_set_shape")
 
 
 def pluq_batched_into(ms, ns, max_m: int, max_n: int, A_packed, A_off, P, P_off, Q, Q_off, rank, rrp, crp,

@@ -553,6 +553,13 @@ int ffp_pluq_batched(int32_t batch, const int32_t *m_arr, const int32_t *n_arr, 
                             Q_off, rank_arr, rrp_packed, crp_packed, ar, (hipStream_t)stream);
 }
 
+int ffp_pluq_batched_set_shape(int32_t batch, int32_t max_m, int32_t max_n, int shape) {
+    if (batch < 0) return -1;
+    if (max_m < 0 || max_m > FFP_BATCH_MAX_DIM) return -2;
+    if (max_n < 0 || max_n > FFP_BATCH_MAX_DIM) return -3;
+    return pluq_batched_set_shape(batch, max_m, max_n, shape);
+}
+
 size_t ffp_pluq_batched_tune_workspace(int32_t batch, int32_t max_m, int32_t max_n, int64_t a_elems) {
     if (batch <= 0) return 0;
     return pluq_batched_ws(batch, max_m, max_n) + (size_t)(a_elems > 0 ? a_elems : 0) * 4 + 512;

@@ -38,8 +38,13 @@ struct BShared {
     BFrame st[kBStack];
     int sp, type, bx, piv, r, job;
     int rord[kBMax], cord[kBMax];
-    double urow[kBMax], vcol[kBMax];
+    int upiv;  // the pivot's value
     int wcnt[kBW + 1];
+    // rows (nonzero multiplier) and columns (active, not the pivot's) of the
+    // next rank-one update, the columns in increasing order
+    short rl[kBMax], cl[kBMax];
+    int nrl, ncl, wtot[16];
+    int np;  // pending pivots not yet applied to the active block
 };
 
 enum { BT_FIN = 0, BT_ROW = 1, BT_COL = 2 };
@@ -150,6 +155,63 @@ __device__ __noinline__ static void bwalk_w(BShared &S, int nwr, int nwc, int la
 
 __global__ void k_batch_reset(int *counter) { *counter = 0; }
 
+// Longest-processing-time order of the queue: jobs sorted by decreasing
+// bucket of m n min(m, n) (the elimination's work), one workgroup, counting
+// sort over 1024 logarithmic buckets (32 per doubling).  Large matrices are
+// taken first so that the last ones to finish are small.
+__global__ __launch_bounds__(1024) void k_batch_order(int32_t batch, const int32_t *__restrict__ m_arr,
+                                                      const int32_t *__restrict__ n_arr, int32_t *__restrict__ order) {
+    __shared__ int hist[1024];
+    const int tid = threadIdx.x;
+    hist[tid] = 0;
+    __syncthreads();
+    auto bucket = [&](int j) {
+        const double m = m_arr[j], n = n_arr[j];
+        const double w = m > 0 && n > 0 ? m * n * (m < n ? m : n) : 0.0;
+        const int b = w >= 1.0 ? (int)(log2(w) * 32.0) : 0;
+        return 1023 - (b < 0 ? 0 : (b > 1023 ? 1023 : b));  // largest first
+    };
+    for (int j = tid; j < batch; j += 1024) atomicAdd(&hist[bucket(j)], 1);
+    __syncthreads();
+    if (tid == 0) {
+        int acc = 0;
+        for (int b = 0; b < 1024; ++b) {
+            const int c = hist[b];
+            hist[b] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    for (int j = tid; j < batch; j += 1024) order[atomicAdd(&hist[bucket(j)], 1)] = j;
+}
+
+// Current Schur-complement value of an entry whose stored value w has not
+// yet received the np pending pivots: w - sum_t L[t] U[t] (L: the row's
+// pending multipliers, U: the pending pivot rows at the entry's column,
+// stride ldu; both centred), exact in FP64 with a reduction every kred terms;
+// canonical result.
+__device__ __forceinline__ double schur_val(int32_t w, const int32_t *L, const int32_t *U, int ldu, int np, int kred,
+                                            double p, double pinv) {
+    double acc = (double)w;
+    int k = 0;
+    for (int t = 0; t < np; ++t) {
+        acc = fma(-(double)L[t], (double)U[t * ldu], acc);
+        if (++k == kred) {
+            acc = mod_near(acc, p, pinv);
+            k = 0;
+        }
+    }
+    return mod_canon(acc, p, pinv);
+}
+
+// Ordered compaction helper: the number of set flags of lanes below this one
+// in the wave, and the wave's total
+__device__ __forceinline__ int wprefix(bool f, int lane, int *tot) {
+    const uint64_t b = __ballot(f);
+    *tot = __popcll(b);
+    return __popcll(b & ((lane ? (~0ull >> (64 - lane)) : 0ull)));
+}
+
 template <int kBT>
 __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32_t *__restrict__ m_arr,
                                                       const int32_t *__restrict__ n_arr, int32_t *__restrict__ A,
@@ -157,14 +219,23 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
                                                       const int64_t *__restrict__ P_off, int32_t *__restrict__ Q,
                                                       const int64_t *__restrict__ Q_off, int32_t *__restrict__ rank,
                                                       int32_t *__restrict__ rrp, int32_t *__restrict__ crp,
-                                                      int *__restrict__ counter, int32_t *__restrict__ slots,
-                                                      int64_t slot_elems, int32_t max_m, int32_t max_n, double p,
-                                                      double pinv, int32_t half) {
+                                                      int *__restrict__ counter, const int32_t *__restrict__ order,
+                                                      int32_t *__restrict__ slots, int64_t slot_elems, int32_t max_m,
+                                                      int32_t max_n, double p, double pinv, int32_t half, int nb,
+                                                      int kred) {
     __shared__ BShared S;
+    // pending pivots (delayed rank-one updates): L[i][t] at Lb[i nb + t],
+    // U[t][j] at Ub[t ldu + j], centred residues
+    extern __shared__ int32_t pend[];
+    int32_t *Lb = pend, *Ub = pend + (size_t)max_m * nb;
+    const int ldu = max_n > 0 ? max_n : 1;
     const int tid = threadIdx.x;
     int32_t *W = slots + (int64_t)blockIdx.x * slot_elems;
     while (true) {
-        if (tid == 0) S.job = atomicAdd(counter, 1);
+        if (tid == 0) {
+            const int t = atomicAdd(counter, 1);
+            S.job = t < batch ? order[t] : batch;
+        }
         __syncthreads();
         const int job = S.job;
         if (job >= batch) break;  // uniform: every wave of the workgroup exits
@@ -209,112 +280,166 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
             S.r = 0;
         }
         __syncthreads();
+        // the first region
+        if (tid < 64) bwalk_w(S, nwr, nwc, tid);
+        if (tid == 0) S.np = 0;
+        __syncthreads();
+        constexpr int NWV = kBT / 64;
+        static_assert(NWV >= 2, "the walk wave and at least one other wave");
+        const int wv = tid >> 6, ln = tid & 63;
         while (true) {
-            if (tid < 64) {
-                bwalk_w(S, nwr, nwc, tid);
-                if (tid == 0) S.piv = INT_MAX;
-            }
-            __syncthreads();
-            const int type = S.type, bx = S.bx;
+            const int type = S.type, bx = S.bx, np = S.np;
             if (type == BT_FIN) break;
-            // search the region for its first nonzero (entries are canonical residues)
+            if (tid == 0) S.piv = INT_MAX;
+            __syncthreads();
+            // search the region for its first nonzero of the current Schur
+            // complement (stored value minus the pending pivots' terms)
             if (type == BT_ROW) {
                 if (bbit(S.nz, bx))
                     for (int c = tid; c < n; c += kBT)
-                        if (bbit(S.mask, c) && W[(int64_t)bx * n + c] != 0) { atomicMin(&S.piv, c); break; }
+                        if (bbit(S.mask, c) &&
+                            schur_val(W[(int64_t)bx * n + c], Lb + bx * nb, Ub + c, ldu, np, kred, p, pinv) != 0.0) {
+                            atomicMin(&S.piv, c);
+                            break;
+                        }
             } else {
                 for (int i = tid; i < m; i += kBT)
-                    if (bbit(S.mask, i) && bbit(S.nz, i) && W[(int64_t)i * n + bx] != 0) { atomicMin(&S.piv, i); break; }
+                    if (bbit(S.mask, i) && bbit(S.nz, i) &&
+                        schur_val(W[(int64_t)i * n + bx], Lb + i * nb, Ub + bx, ldu, np, kred, p, pinv) != 0.0) {
+                        atomicMin(&S.piv, i);
+                        break;
+                    }
             }
             __syncthreads();
             const int pv = S.piv;
-            if (pv == INT_MAX) continue;
+            if (pv != INT_MAX) {
             const int x = type == BT_ROW ? bx : pv, y = type == BT_ROW ? pv : bx;
-            // pivot row (final U entries) and pivot column to LDS
+            // the pivot row's final U entries (pending terms applied), kept as
+            // pending row np (centred) for the later corrections
             for (int c = tid; c < n; c += kBT)
-                if (!bbit(S.coldone, c)) S.urow[c] = (double)W[(int64_t)x * n + c];
-            for (int i = tid; i < m; i += kBT)
-                if (!bbit(S.rowdone, i) && i != x) S.vcol[i] = (double)W[(int64_t)i * n + y];
+                if (!bbit(S.coldone, c)) {
+                    const double u = schur_val(W[(int64_t)x * n + c], Lb + x * nb, Ub + c, ldu, np, kred, p, pinv);
+                    if (c == y) S.upiv = (int32_t)u;
+                    W[(int64_t)x * n + c] = (int32_t)u;
+                    Ub[np * ldu + c] = (int32_t)centre((int32_t)u, p, half);
+                }
             __syncthreads();
-            const double inv = (double)inv_mod((int32_t)S.urow[y], (int32_t)p);
-            // multipliers (final L entries)
-            for (int i = tid; i < m; i += kBT) {
-                if (bbit(S.rowdone, i) || i == x) continue;
-                const double l = mod_canon(S.vcol[i] * inv, p, pinv);
-                S.vcol[i] = l;
-                W[(int64_t)i * n + y] = (int32_t)l;
+            if (wv == 0) {
+                // wave 0 records the pivot and walks to the next region while
+                // the others form the L column (the walk reads the done masks
+                // and the nonzero-row bits, which stay a superset of the true ones)
+                if (ln == 0) {
+                    S.rowdone[x >> 5] |= 1u << (x & 31);
+                    S.coldone[y >> 5] |= 1u << (y & 31);
+                    S.rord[x] = S.r;
+                    S.cord[y] = S.r;
+                    S.r += 1;
+                    S.np = np + 1;
+                }
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                bwalk_w(S, nwr, nwc, ln);
+            } else {
+                // the pivot column's final L entries, kept as pending column np
+                const int32_t piv = S.upiv;
+                const double inv =
+                    (double)(p < 16777216.0 ? inv_mod_small(piv, (int32_t)p) : inv_mod(piv, (int32_t)p));
+                for (int i = tid - 64; i < m; i += kBT - 64)
+                    if (i != x && !bbit(S.rowdone, i)) {
+                        const double s = schur_val(W[(int64_t)i * n + y], Lb + i * nb, Ub + y, ldu, np, kred, p, pinv);
+                        const double l = mod_canon(s * inv, p, pinv);
+                        W[(int64_t)i * n + y] = (int32_t)l;
+                        Lb[i * nb + np] = (int32_t)centre((int32_t)l, p, half);
+                    }
             }
             __syncthreads();
-            // rank-one update of the active block: wave w takes rows w*RU ..,
-            // RU rows at a time, lane c the columns c, c + 64, .., so that every
-            // lane has RU x CH independent loads in flight (sixteen waves: 64
-            // rows per round of loads)
-            {
-                constexpr int RU = 4, CH = 4;
-                const int wv = tid >> 6, ln = tid & 63, nch = (n + 63) >> 6;
-                for (int i0 = wv * RU; i0 < m; i0 += (kBT / 64) * RU) {
-                    double l[RU];
-                    bool nzr[RU];
+            }
+            // ---- flush: apply the pending pivots to the active block at once
+            // when nb are pending, or when a region turned out empty (the
+            // nonzero-row bits are refreshed only here, so an empty region
+            // means they may be stale: refreshed, they prune the walk again)
+            const int npf = S.np;
+            if (npf >= nb || (pv == INT_MAX && npf > 0)) {
+            // ---- flush: apply the pending pivots to the active block at
+            // once (one read and one write per entry for nb pivots); the rows
+            // with a nonzero pending multiplier and the active columns compacted
+            int wt_r = 0, wt_c = 0;
 #pragma unroll
-                    for (int r = 0; r < RU; ++r) {
-                        const int i = i0 + r;
-                        const bool act = i < m && !bbit(S.rowdone, i) && i != x;
-                        l[r] = act ? S.vcol[i] : 0.0;
-                        nzr[r] = false;
+            for (int k = 0; k < (kBMax + kBT - 1) / kBT; ++k) {
+                const int i = tid + k * kBT;
+                bool f = false;
+                if (i < m && !bbit(S.rowdone, i)) {
+                    for (int t = 0; t < npf; ++t) f |= Lb[i * nb + t] != 0;
+                }
+                int t;
+                const int pr = wprefix(f, ln, &t);
+                wt_r = t;
+                const bool fc = i < n && !bbit(S.coldone, i);
+                const int pc = wprefix(fc, ln, &t);
+                wt_c = t;
+                if (ln == 0) S.wtot[wv] = wt_r | (wt_c << 16);
+                __syncthreads();
+                if (tid == 0) {
+                    int ar = k == 0 ? 0 : S.nrl, ac = k == 0 ? 0 : S.ncl;
+                    for (int w = 0; w < NWV; ++w) {
+                        const int v = S.wtot[w];
+                        S.wtot[w] = ar | (ac << 16);
+                        ar += v & 0xffff;
+                        ac += v >> 16;
                     }
+                    S.nrl = ar;
+                    S.ncl = ac;
+                }
+                __syncthreads();
+                const int base = S.wtot[wv];
+                if (f) S.rl[(base & 0xffff) + pr] = (short)i;
+                if (fc) S.cl[(base >> 16) + pc] = (short)i;
+                __syncthreads();
+            }
+            {
+                const int nrl = S.nrl, ncl = S.ncl;
+                constexpr int CH = 4;
+                const int nch = (ncl + 63) >> 6;
+                for (int q = wv; q < nrl; q += NWV) {
+                    const int i = S.rl[q];
+                    const int32_t *Lr = Lb + i * nb;
+                    bool nzr = false;
                     for (int ch0 = 0; ch0 < nch; ch0 += CH) {
-                        int32_t v[RU][CH];
-                        double u[CH];
+                        int col[CH];
                         bool ok[CH];
+                        int32_t v[CH];
 #pragma unroll
                         for (int cc = 0; cc < CH; ++cc) {
-                            const int c = ln + 64 * (ch0 + cc);
-                            ok[cc] = c < n && c != y && !bbit(S.coldone, c);
-                            u[cc] = ok[cc] ? S.urow[c] : 0.0;
+                            const int qq = ln + 64 * (ch0 + cc);
+                            ok[cc] = qq < ncl;
+                            col[cc] = S.cl[ok[cc] ? qq : ncl - 1];
                         }
-                        // unconditional loads at clamped addresses (a guarded load
-                        // waits before the next is issued); unused values are ignored
 #pragma unroll
-                        for (int r = 0; r < RU; ++r)
+                        for (int cc = 0; cc < CH; ++cc) v[cc] = W[(int64_t)i * n + col[cc]];
 #pragma unroll
-                            for (int cc = 0; cc < CH; ++cc) {
-                                const int ir = i0 + r < m ? i0 + r : m - 1;
-                                const int c = ln + 64 * (ch0 + cc) < n ? ln + 64 * (ch0 + cc) : n - 1;
-                                v[r][cc] = W[(int64_t)ir * n + c];
-                            }
-#pragma unroll
-                        for (int r = 0; r < RU; ++r)
-#pragma unroll
-                            for (int cc = 0; cc < CH; ++cc) {
-                                const int c = ln + 64 * (ch0 + cc);
-                                if (l[r] != 0.0 && ok[cc]) {
-                                    const int32_t nv = (int32_t)mod_canon((double)v[r][cc] - l[r] * u[cc], p, pinv);
-                                    W[(int64_t)(i0 + r) * n + c] = nv;
-                                    nzr[r] |= nv != 0;
-                                }
-                            }
+                        for (int cc = 0; cc < CH; ++cc) {
+                            if (!ok[cc]) continue;
+                            const int32_t nv = (int32_t)schur_val(v[cc], Lr, Ub + col[cc], ldu, npf, kred, p, pinv);
+                            W[(int64_t)i * n + col[cc]] = nv;
+                            nzr |= nv != 0;
+                        }
                     }
-                    // rows with a nonzero multiplier changed: refresh their bit (a
-                    // row with a zero multiplier keeps its entries and its bit)
-#pragma unroll
-                    for (int r = 0; r < RU; ++r) {
-                        const bool any = __ballot(nzr[r]) != 0ull;
-                        const int i = i0 + r;
-                        if (ln == 0 && l[r] != 0.0) {
-                            if (any) atomicOr(&S.nz[i >> 5], 1u << (i & 31));
-                            else atomicAnd(&S.nz[i >> 5], ~(1u << (i & 31)));
-                        }
+                    // a listed row's active entries are the listed columns
+                    const bool any = __ballot(nzr) != 0ull;
+                    if (ln == 0) {
+                        if (any) atomicOr(&S.nz[i >> 5], 1u << (i & 31));
+                        else atomicAnd(&S.nz[i >> 5], ~(1u << (i & 31)));
                     }
                 }
             }
-            if (tid == 0) {
-                S.rowdone[x >> 5] |= 1u << (x & 31);
-                S.coldone[y >> 5] |= 1u << (y & 31);
-                S.rord[x] = S.r;
-                S.cord[y] = S.r;
-                S.r += 1;
-            }
+            if (tid == 0) S.np = 0;
             __syncthreads();
+            }
+            if (pv == INT_MAX) {
+                // no pivot in the region: walk on to the next one
+                if (tid < 64) bwalk_w(S, nwr, nwc, tid);
+                __syncthreads();
+            }
         }
         // ---- output order: pivots in order, then the rest ascending
         const int r = S.r;
@@ -350,9 +475,13 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
             }
         }
         __syncthreads();
+        // the block of non-pivot rows and columns is zero in the final
+        // factorisation (every pivot has been found); the slot may still hold
+        // its entries without the last pending pivots' terms
         for (int64_t e = tid; e < (int64_t)m * n; e += kBT) {
             const int i = (int)(e / n), c = (int)(e % n);
-            Aj[(int64_t)S.rord[i] * n + S.cord[c]] = W[e];
+            const bool keep = bbit(S.rowdone, i) || bbit(S.coldone, c);
+            Aj[(int64_t)S.rord[i] * n + S.cord[c]] = keep ? W[e] : 0;
         }
         int32_t *Pj = P + P_off[job], *Qj = Q + Q_off[job];
         for (int i = tid; i < m; i += kBT) Pj[S.rord[i]] = i;
@@ -376,14 +505,15 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
 
 // Launch shapes (threads per workgroup, workgroups per compute unit): one
 // 1024-thread workgroup per CU (sixteen waves on each matrix, the default),
-// or two 256-thread workgroups per CU (twice the matrices in flight, a
-// quarter of the waves on each).  ffp_pluq_batched_tune times them on the
+// or several smaller workgroups per CU (more matrices in flight, whose
+// latency-bound pivot chains then overlap, fewer waves on each).  ffp_pluq_batched_tune times them on the
 // caller's batch and keeps the faster one for batches of that description.
 struct BShape {
     int threads, per_cu;
 };
-constexpr BShape kShapes[] = {{1024, 1}, {256, 2}};
+constexpr BShape kShapes[] = {{1024, 1}, {512, 2}, {256, 3}, {256, 2}};
 constexpr int kNShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+static_assert(kNShapes == FFP_BATCH_SHAPES, "the header states the number of launch shapes");
 
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int, int>, int> g_tuned;  // (device, batch, max_m, max_n) -> shape
@@ -405,7 +535,7 @@ static int max_grid(int32_t batch) {
 
 size_t pluq_batched_ws(int32_t batch, int32_t max_m, int32_t max_n) {
     const size_t slot = (size_t)(max_m > 0 ? max_m : 1) * (size_t)(max_n > 0 ? max_n : 1);
-    return 256 + (size_t)max_grid(batch) * slot * 4 + 256;
+    return 256 + (size_t)(batch > 0 ? batch : 0) * 4 + 256 + (size_t)max_grid(batch) * slot * 4 + 256;
 }
 
 static int tuned_shape(int32_t batch, int32_t max_m, int32_t max_n) {
@@ -422,18 +552,29 @@ static int launch_shape(int shape, const Field &F, int32_t batch, const int32_t 
                         int32_t *crp, Arena &ws, hipStream_t s) {
     const size_t mk = ws.mark();
     int *counter = (int *)ws.take(256);
+    int32_t *order = (int32_t *)ws.take((size_t)batch * 4);
     const int grid = batched_grid(batch, shape);
     const int64_t slot = (int64_t)(max_m > 0 ? max_m : 1) * (int64_t)(max_n > 0 ? max_n : 1);
     int32_t *slots = (int32_t *)ws.take((size_t)grid * (size_t)slot * 4);
-    if (!counter || !slots) return FFP_E_WORKSPACE;
+    if (!counter || !order || !slots) return FFP_E_WORKSPACE;
+    // pending-pivot buffers in LDS: as many pivots as the shape's share of
+    // the compute unit's 160 KiB leaves room for (at most 16)
+    const int64_t budget = (int64_t)(160 * 1024) / kShapes[shape].per_cu - (int64_t)sizeof(BShared) - 1024;
+    const int64_t per = 4 * (int64_t)((max_m > 0 ? max_m : 1) + (max_n > 0 ? max_n : 1));
+    int nb = (int)std::min<int64_t>(16, budget / per);
+    if (nb < 1) nb = 1;
+    const int kred = (int)std::min<int64_t>(nb, F.kexact > 0 ? F.kexact : 1);
+    const size_t dyn = (size_t)nb * (size_t)per;
     // counter cleared by a kernel (not a memset) so that the sequence can be captured in a graph
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, counter);
+    hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, s, batch, m_arr, n_arr, order);
     ProfScope prof(PK_BATCHED, 0.0, s, 0.0);
-#define FFP_BAT(T_)                                                                                          \
-    hipLaunchKernelGGL((k_pluq_batched<T_>), dim3(grid), dim3(T_), 0, s, batch, m_arr, n_arr, A, A_off, P, P_off, \
-                       Q, Q_off, rank, rrp, crp, counter, slots, slot, max_m, max_n, F.pd, F.pinv, \
-                       (int32_t)F.half)
+#define FFP_BAT(T_)                                                                                            \
+    hipLaunchKernelGGL((k_pluq_batched<T_>), dim3(grid), dim3(T_), dyn, s, batch, m_arr, n_arr, A, A_off, P, P_off, \
+                       Q, Q_off, rank, rrp, crp, counter, order, slots, slot, max_m, max_n, F.pd, F.pinv,        \
+                       (int32_t)F.half, nb, kred)
     if (kShapes[shape].threads == 1024) FFP_BAT(1024);
+    else if (kShapes[shape].threads == 512) FFP_BAT(512);
     else FFP_BAT(256);
 #undef FFP_BAT
     FFP_HIP_CHECK(hipGetLastError());
@@ -496,6 +637,18 @@ int pluq_batched_tune(const Field &F, int32_t batch, const int32_t *m_arr, const
         g_tuned[std::make_tuple(dev, batch, max_m, max_n)] = best;
     }
     if (chosen) *chosen = best;
+    return FFP_OK;
+}
+
+// Record a launch shape for batches of this description (what the tuner
+// stores after timing): later ffp_pluq_batched calls with the same (device,
+// batch, max_m, max_n) use it.
+int pluq_batched_set_shape(int32_t batch, int32_t max_m, int32_t max_n, int shape) {
+    if (shape < 0 || shape >= kNShapes) return -4;
+    int dev = 0;
+    FFP_HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tuned[std::make_tuple(dev, batch, max_m, max_n)] = shape;
     return FFP_OK;
 }
 

@@ -225,6 +225,7 @@ int check_range_run(int64_t m, int64_t n, uint32_t p, const int32_t *A, int64_t 
 size_t pluq_slab_ws(int64_t m, int64_t n, const Field &F, int path);
 int pluq_slab_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
                   int64_t *r, Arena &ws, hipStream_t s);
+int pluq_batched_set_shape(int32_t batch, int32_t max_m, int32_t max_n, int shape);
 // a pinned, device-visible host word for one rank / flag read-back (pooled)
 struct RankWord {
     int64_t *host = nullptr, *dev = nullptr;

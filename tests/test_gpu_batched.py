@@ -199,3 +199,20 @@ def test_batched_autotune(lib, orc):
     out = (A2.cpu().numpy(), res2.P.cpu().numpy(), res2.Q.cpu().numpy(), res2.rank.cpu().numpy(),
            res2.rrp.cpu().numpy(), res2.crp.cpu().numpy())
     _compare(orc, ms, ns, A, off, p, out, range(0, len(ms), 25))
+
+
+def test_batched_every_launch_shape(lib, orc):
+    """Each launch shape, chosen explicitly, gives the oracle's bits on a
+    mixed batch (shapes differ in workgroup size, so in the compaction
+    rounds and the number of update waves)."""
+    import torch
+    p = 65521
+    ms, ns, rs, A, off = wl.batch(120, 16, 400, p, 33)
+    max_m, max_n = int(ms.max()), int(ns.max())
+    for shape in range(lib.BATCH_SHAPES):
+        note("batched shape", shape)
+        lib.pluq_batched_set_shape(len(ms), max_m, max_n, shape)
+        out = _run(lib, ms, ns, A, off, p)
+        assert np.array_equal(out[3][:len(ms)], rs), shape
+        _compare(orc, ms, ns, A, off, p, out, range(len(ms)))
+    lib.pluq_batched_set_shape(len(ms), max_m, max_n, 0)
