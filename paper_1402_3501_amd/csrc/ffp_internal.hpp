@@ -196,10 +196,13 @@ int copy2d(int64_t m, int64_t n, const int32_t *src, int64_t lds, int32_t *dst, 
 // dimension lda); Pd / Pe (a full 64 x 64 block with inverses) are replaced
 // after it by L^-1 Pd (64 x pdn) and Pe U^-1 (pem x 64).  A zero pivot sets
 // *gflag = 1 + its index on the whole diagonal (diag0: the block's offset).
+// General leaf with gen_done non-null: the generic leaf ran first with that
+// flag; if it stayed clear only P, Q and the rank are written.
 int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
                   int64_t *rank_dev, int *gflag, double *Linv, double *Uinv, hipStream_t s,
                   const int32_t *He = nullptr, const int32_t *Hd = nullptr, int32_t *Pd = nullptr,
-                  int64_t pdn = 0, int32_t *Pe = nullptr, int64_t pem = 0, int64_t diag0 = 0);
+                  int64_t pdn = 0, int32_t *Pe = nullptr, int64_t pem = 0, int64_t diag0 = 0,
+                  const int *gen_done = nullptr);
 
 // PLUQ (host recursion); P, Q device outputs (local indices); returns rank via *r
 int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P,

@@ -49,15 +49,25 @@ __device__ __forceinline__ double cen(double x, double p, double pinv, double hd
     return c > hd ? c - p : c;
 }
 
+// gen_done non-null: the generic leaf ran on the block just before, with
+// *gen_done as its zero-pivot flag; when it stayed clear the block holds its
+// LU already (identity permutations, full rank) and only P, Q and the rank
+// are written here, otherwise the block is untouched and factored below.
 template <bool RED, bool SMALLP>
 __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restrict__ A, int64_t lda,
                                               int32_t *__restrict__ P, int32_t *__restrict__ Q,
                                               int64_t *__restrict__ rank_out, double p, double pinv, int32_t half,
-                                              int64_t kexact) {
+                                              int64_t kexact, const int *__restrict__ gen_done) {
     __shared__ double W[64][65];
     __shared__ double Lc[64];
     __shared__ int rord[64], cord[64];
     const int lane = threadIdx.x;
+    if (gen_done && __builtin_amdgcn_readfirstlane(*(volatile const int *)gen_done) == 0) {
+        if (lane < mb) P[lane] = lane;
+        if (lane < nb) Q[lane] = lane;
+        if (lane == 0) *(volatile int64_t *)rank_out = mb < nb ? mb : nb;
+        return;
+    }
     const uint64_t allr = mb >= 64 ? ~0ull : ((1ull << mb) - 1ull);
     const uint64_t allc = nb >= 64 ? ~0ull : ((1ull << nb) - 1ull);
     {
@@ -618,12 +628,13 @@ constexpr int kGenWaves = 8;
 
 int leaf64_launch(const Field &F, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q,
                   int64_t *rank_dev, int *gflag, double *Linv, double *Uinv, hipStream_t s, const int32_t *He,
-                  const int32_t *Hd, int32_t *Pd, int64_t pdn, int32_t *Pe, int64_t pem, int64_t diag0) {
+                  const int32_t *Hd, int32_t *Pd, int64_t pdn, int32_t *Pe, int64_t pem, int64_t diag0,
+                  const int *gen_done) {
     const bool red = F.kexact < 64;
     const bool small = F.p < (1u << 24);
 #define FFP_L64(R_, S_)                                                                                    \
     hipLaunchKernelGGL((k_leaf64<R_, S_>), dim3(1), dim3(64), 0, s, (int)m, (int)n, A, lda, P, Q, rank_dev, \
-                       F.pd, F.pinv, (int32_t)F.half, F.kexact)
+                       F.pd, F.pinv, (int32_t)F.half, F.kexact, gen_done)
 #define FFP_SEL(X_)                                     \
     if (red) {                                          \
         if (small) X_(true, true); else X_(true, false); \

@@ -660,7 +660,19 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
     }
     const Field &F = *c.F;
     if (leaf64_fits(m, n)) {
-        FFP_CHECK(leaf64_launch(F, m, n, A, lda, P, Q, c.rank_dev, nullptr, nullptr, nullptr, s));
+        // most blocks of an input whose rank profile is generic almost
+        // everywhere (a uniform matrix mod a small prime) are themselves
+        // generic: the eight-wave generic leaf is tried first (it writes the
+        // block only when every pivot is nonzero), the one-wave general leaf
+        // then only writes P, Q and the rank, or factors the untouched block
+        const int *gen_done = nullptr;
+        if (m >= 16 && n >= 16) {
+            hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c.flag_dev, 0);
+            FFP_CHECK(leaf64_launch(F, m, n, A, lda, nullptr, nullptr, nullptr, c.flag_dev, nullptr, nullptr, s));
+            gen_done = c.flag_dev;
+        }
+        FFP_CHECK(leaf64_launch(F, m, n, A, lda, P, Q, c.rank_dev, nullptr, nullptr, nullptr, s, nullptr, nullptr,
+                                nullptr, 0, nullptr, 0, 0, gen_done));
         return read_rank(c, rank);
     }
     if (leaf_fits(m, n)) {
