@@ -65,7 +65,8 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
     if (gen_done && __builtin_amdgcn_readfirstlane(*(volatile const int *)gen_done) == 0) {
         if (lane < mb) P[lane] = lane;
         if (lane < nb) Q[lane] = lane;
-        if (lane == 0) *(volatile int64_t *)rank_out = mb < nb ? mb : nb;
+        // rank, with both permutations flagged as the identity (bits 40, 41)
+        if (lane == 0) *(volatile int64_t *)rank_out = (int64_t)(mb < nb ? mb : nb) | (3ll << 40);
         return;
     }
     const uint64_t allr = mb >= 64 ? ~0ull : ((1ull << mb) - 1ull);
@@ -315,7 +316,10 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
         Q[cp] = lane;
     }
     if (lane < mb) P[rord[lane]] = lane;
-    if (lane == 0) *rank_out = r;
+    // the rank, with bit 40 / 41 set when P / Q is the identity
+    const bool pid = __ballot(lane < mb && rord[lane] != lane) == 0ull;
+    const bool qid = __ballot(lane < nb && cord[lane] != lane) == 0ull;
+    if (lane == 0) *rank_out = (int64_t)r | ((int64_t)pid << 40) | ((int64_t)qid << 41);
 }
 
 // Leaf of the generic-rank-profile factorisation (plain LU: pivots (k, k)),

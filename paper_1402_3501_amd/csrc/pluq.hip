@@ -643,19 +643,25 @@ int block_is_zero(Ctx &c, int64_t m, int64_t n, const int32_t *A, int64_t lda, b
     return FFP_OK;
 }
 
-int pluq_sub(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q, int64_t *rank);
+// *pid / *qid: set when the block's P / Q came out as the identity, so that
+// the parent can skip applying them
+int pluq_sub(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q, int64_t *rank, bool *pid,
+             bool *qid);
 
 // gen_ok: every leading minor of this block up to that order is known to be
 // nonzero (from a failed generic attempt on a block with the same top-left
 // corner); a leading tile within that order is then factored as a plain LU.
 int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q, int64_t *rank,
-             int64_t gen_ok) {
+             int64_t gen_ok, bool *pid, bool *qid) {
     hipStream_t s = c.s;
     Arena &ws = *c.ws;
+    *pid = false;
+    *qid = false;
     if (m == 0 || n == 0) {
         FFP_CHECK(iota(P, m, s));
         FFP_CHECK(iota(Q, n, s));
         *rank = 0;
+        *pid = *qid = true;
         return FFP_OK;
     }
     const Field &F = *c.F;
@@ -673,7 +679,12 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
         }
         FFP_CHECK(leaf64_launch(F, m, n, A, lda, P, Q, c.rank_dev, nullptr, nullptr, nullptr, s, nullptr, nullptr,
                                 nullptr, 0, nullptr, 0, 0, gen_done));
-        return read_rank(c, rank);
+        int64_t word = 0;
+        FFP_CHECK(read_rank(c, &word));
+        *rank = word & ((1ll << 40) - 1);
+        *pid = (word >> 40) & 1;
+        *qid = (word >> 41) & 1;
+        return FFP_OK;
     }
     if (leaf_fits(m, n)) {
         const bool red = F.kexact < kLMaxDim;
@@ -690,6 +701,7 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
     const int64_t m1 = m / 2, n1 = n / 2;
     // ---- 1. top-left tile (same corner: same leading minors)
     int64_t r1 = 0;
+    bool p1id = false, q1id = false;
     {
         const int64_t k1 = m1 < n1 ? m1 : n1;
         bool gen = false;
@@ -699,13 +711,14 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
             FFP_CHECK(iota(P, m1, s));
             FFP_CHECK(iota(Q, n1, s));
             r1 = k1;
+            p1id = q1id = true;
         } else {
-            FFP_CHECK(pluq_rec(c, m1, n1, A, lda, P, Q, &r1, gen_ok));
+            FFP_CHECK(pluq_rec(c, m1, n1, A, lda, P, Q, &r1, gen_ok, &p1id, &q1id));
         }
     }
-    // ---- 2. [B1; B2] = P1^T A2,  [C1 C2] = A3 Q1^T
-    FFP_CHECK(rows_perm(c, m1, n - n1, A + n1, lda, P));
-    FFP_CHECK(cols_perm(c, m - m1, n1, A + m1 * lda, lda, Q));
+    // ---- 2. [B1; B2] = P1^T A2,  [C1 C2] = A3 Q1^T  (identities skipped)
+    if (!p1id) FFP_CHECK(rows_perm(c, m1, n - n1, A + n1, lda, P));
+    if (!q1id) FFP_CHECK(cols_perm(c, m - m1, n1, A + m1 * lda, lda, Q));
     // ---- 3. D = L1^-1 B1, E = C1 U1^-1, [F; H] -= [M1; E] D, G = C2 - E V1
     FFP_CHECK(node_updates(c, m, n, m1, n1, r1, A, lda));
     // ---- 4. factor F (top-right remainder) and G (bottom-left remainder)
@@ -717,16 +730,19 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
     if ((!P2 && m1 - r1 > 0) || (!Q2 && n - n1 > 0) || (!P3 && m - m1 > 0) || (!Q3 && n1 - r1 > 0))
         return FFP_E_WORKSPACE;
     int64_t r2 = 0, r3 = 0;
-    FFP_CHECK(pluq_sub(c, m1 - r1, n - n1, A + r1 * lda + n1, lda, P2, Q2, &r2));
-    FFP_CHECK(pluq_sub(c, m - m1, n1 - r1, A + m1 * lda + r1, lda, P3, Q3, &r3));
+    bool p2id = false, q2id = false, p3id = false, q3id = false;
+    FFP_CHECK(pluq_sub(c, m1 - r1, n - n1, A + r1 * lda + n1, lda, P2, Q2, &r2, &p2id, &q2id));
+    FFP_CHECK(pluq_sub(c, m - m1, n1 - r1, A + m1 * lda + r1, lda, P3, Q3, &r3, &p3id, &q3id));
     // ---- 5. carry the sub-permutations to the rest of their rows / columns
     if (r1 > 0) {
-        FFP_CHECK(rows_perm(c, m1 - r1, r1, A + r1 * lda, lda, P2));                 // M1
-        FFP_CHECK(cols_perm(c, r1, n1 - r1, A + r1, lda, Q3));                       // V1
-        FFP_CHECK(rows_perm(c, m - m1, r1, A + m1 * lda, lda, P3));                  // E
-        FFP_CHECK(cols_perm(c, r1, n - n1, A + n1, lda, Q2));                        // D
+        if (!p2id) FFP_CHECK(rows_perm(c, m1 - r1, r1, A + r1 * lda, lda, P2));   // M1
+        if (!q3id) FFP_CHECK(cols_perm(c, r1, n1 - r1, A + r1, lda, Q3));         // V1
+        if (!p3id) FFP_CHECK(rows_perm(c, m - m1, r1, A + m1 * lda, lda, P3));    // E
+        if (!q2id) FFP_CHECK(cols_perm(c, r1, n - n1, A + n1, lda, Q2));          // D
     }
-    FFP_CHECK(permute_inplace(m - m1, n - n1, A + m1 * lda + n1, lda, by_index(P3), by_index(Q2), ws, s));  // H
+    if (!p3id || !q2id)                                                           // H
+        FFP_CHECK(permute_inplace(m - m1, n - n1, A + m1 * lda + n1, lda, p3id ? PermSpec() : by_index(P3),
+                                  q2id ? PermSpec() : by_index(Q2), ws, s));
     // ---- 6. [I; K] = [H1; H3] U2^-1, O = L3^-1 (H2 - I V2), R = H4 - K V2 - M3 O
     int32_t *const H = A + m1 * lda + n1;
     if (r2 > 0) FFP_CHECK(trsm_sub(c, 1, 1, 0, m - m1, r2, A + r1 * lda + n1, lda, H, lda));
@@ -742,9 +758,10 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
     int32_t *Q4 = (int32_t *)ws.take((size_t)(n - n1 - r2) * 4);
     if ((!P4 && m - m1 - r3 > 0) || (!Q4 && n - n1 - r2 > 0)) return FFP_E_WORKSPACE;
     int64_t r4 = 0;
-    FFP_CHECK(pluq_sub(c, m - m1 - r3, n - n1 - r2, R, lda, P4, Q4, &r4));
-    FFP_CHECK(rows_perm(c, m - m1 - r3, n1 + r2, A + (m1 + r3) * lda, lda, P4));
-    FFP_CHECK(cols_perm(c, m1 + r3, n - n1 - r2, A + n1 + r2, lda, Q4));
+    bool p4id = false, q4id = false;
+    FFP_CHECK(pluq_sub(c, m - m1 - r3, n - n1 - r2, R, lda, P4, Q4, &r4, &p4id, &q4id));
+    if (!p4id) FFP_CHECK(rows_perm(c, m - m1 - r3, n1 + r2, A + (m1 + r3) * lda, lda, P4));
+    if (!q4id) FFP_CHECK(cols_perm(c, m1 + r3, n - n1 - r2, A + n1 + r2, lda, Q4));
     // ---- 8. final rotations: rows [a f f' g R r'] -> [a f g R f' r'],
     //         columns [a g g' f R c'] -> [a f g R g' c']
     {
@@ -781,20 +798,26 @@ int pluq_rec(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, 
     }
     ws.release(mk);
     *rank = r1 + r2 + r3 + r4;
+    // the node's rows keep their order when A1 has full row rank (F has no
+    // rows) and every sub-block's row order is the identity; columns alike
+    *pid = r1 == m1 && p1id && p3id && p4id;
+    *qid = r1 == n1 && q1id && q2id && q4id;
     return FFP_OK;
 }
 
 // F, G and R of a node: a zero block is factored by its identity permutations
-int pluq_sub(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q, int64_t *rank) {
+int pluq_sub(Ctx &c, int64_t m, int64_t n, int32_t *A, int64_t lda, int32_t *P, int32_t *Q, int64_t *rank, bool *pid,
+             bool *qid) {
     bool zero = false;
     if (m > 0 && n > 0) FFP_CHECK(block_is_zero(c, m, n, A, lda, &zero));
     if (zero) {
         FFP_CHECK(iota(P, m, c.s));
         FFP_CHECK(iota(Q, n, c.s));
         *rank = 0;
+        *pid = *qid = true;
         return FFP_OK;
     }
-    return pluq_rec(c, m, n, A, lda, P, Q, rank, 0);
+    return pluq_rec(c, m, n, A, lda, P, Q, rank, 0, pid, qid);
 }
 }  // namespace
 
@@ -948,7 +971,8 @@ int pluq_run(int path, const Field &F, int64_t m, int64_t n, int32_t *A, int64_t
             return FFP_OK;
         }
     }
-    return pluq_rec(c, m, n, A, lda, P, Q, r, gen_ok);
+    bool pid = false, qid = false;
+    return pluq_rec(c, m, n, A, lda, P, Q, r, gen_ok, &pid, &qid);
 }
 
 // Plain LU of an input of generic rank profile, asynchronous (ffp_lu_nopiv):
