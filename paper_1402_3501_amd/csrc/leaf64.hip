@@ -90,9 +90,11 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
     // elimination is nonzero, the leading minors are all nonzero, the pivots
     // are (k, k) and the quadrant order is the identity, so no walk and no
     // search are needed.  A zero pivot sends the block to the general walk.
+    // (skipped when the generic leaf already found a zero pivot in this block)
     const int kd = mb < nb ? mb : nb;
-    bool generic = true;
-    for (int k = 0; k < kd; ++k) {
+    const bool try_generic_pass = gen_done == nullptr;
+    bool generic = try_generic_pass;
+    for (int k = 0; k < (try_generic_pass ? kd : 0); ++k) {
         double u = 0.0;
         if (lane < nb && lane >= k) {
             const double c = mod_canon(W[k][lane], p, pinv);
@@ -144,7 +146,7 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
         r = kd;
         rowdone = kd >= 64 ? ~0ull : ((1ull << kd) - 1ull);
         coldone = rowdone;
-    } else {
+    } else if (try_generic_pass) {
         // restart from the untouched input with the general walk
         cnt = 0;
         int32_t av[64];
