@@ -22,7 +22,12 @@ when their kernel source hash still matches.
 Also printed (outside the timed steps): the same PLUQ forced onto each
 path with bit-exact agreement, the n^3 product on both paths, and every
 other configuration: 512 x 512 mod 65521, 8192 x 8192 mod 131071 (uniform
-and rank 4096), 16384 mod 251 (one limb), the batched workload.  The CPU
+and rank 4096), 16384 mod 251 (one limb), the batched workload; the
+Strassen-Winograd products against the plain ones at 8192 and at the
+workload size; the factorisation variants at 8192 (tile-iterative
+right-looking, Crout and left-looking with their modelled reduction counts,
+slab-recursive) against the tile recursion; echelon form and nullspace of
+the rank-4096 input.  The CPU
 baseline is the plain oracle, on all host threads on the leading block of
 the workload matrix, and on one thread on the 512 x 512 matrix and on a
 sample of the batched workload.
@@ -167,6 +172,14 @@ def main():
     for name, (nl, kms, kops, kbytes) in sorted(fams.items(), key=lambda x: -x[1][1]):
         families[name] = {"launches_per_step": round(nl / K, 2), "ms_per_step": round(kms / K, 4),
                           "avg_launch_us": round(kms * 1e3 / nl, 3), "share_of_step": round(kms / K / ms, 4)}
+        # algorithmic rate against the peak of the unit the family runs on
+        # (INT8 products count their L^2 digit products)
+        if kops > 0:
+            peak = PEAK_INT8 if name == "k_fgemm_i8" else PEAK_FP64
+            ops = kops * (L * L if name == "k_fgemm_i8" else 1)
+            families[name]["frac_of_peak"] = round(ops / (kms * 1e-3) / peak, 6)
+        elif kbytes > 0:
+            families[name]["frac_of_hbm"] = round(kbytes / (kms * 1e-3) / PEAK_HBM, 4)
     dom = max(fams, key=lambda x: fams[x][1]) if fams else None
     roof = None
     if dom:
@@ -297,6 +310,75 @@ def main():
             if name in ("pluq8192_p131071", "n16384_p251"):
                 for kk, v in fgemm_pair(nn2, p2, 302).items():
                     extra[f"{name}_{kk}"] = v
+        # Strassen-Winograd over the n^3 product (automatic levels and one
+        # level) against the plain product, both paths, bit-exact
+        log("[bench] Strassen-Winograd products ...")
+        for nn, p2 in ((8192, 131071), (n, p)):
+            X = torch.from_numpy(wl.uniform(nn, nn, p2, 501)).to(dev)
+            Y = torch.from_numpy(wl.uniform(nn, nn, p2, 502)).to(dev)
+            for pth, pn in ((ffp.PATH_INT8, "int8"), (ffp.PATH_FP64, "fp64")):
+                if pth == ffp.PATH_INT8 and ffp.int8_limbs(p2) == 0:
+                    continue
+                Z0 = torch.zeros((nn, nn), dtype=torch.int32, device=dev)
+                t0_, _ = timed(lambda: ffp.fgemm(X, Y, Z0, p2, path=pth), 2)
+                for lv, ln_ in ((ffp.WINO_AUTO, "auto"), (1, "1")):
+                    Z = torch.zeros((nn, nn), dtype=torch.int32, device=dev)
+                    t_, _ = timed(lambda: ffp.fgemm_wino(X, Y, Z, p2, path=pth, levels=lv), 2)
+                    key = f"fgemm{nn}_p{p2}_{pn}"
+                    extra[f"{key}_plain_ms"] = round(t0_, 3)
+                    extra[f"{key}_wino{ln_}_ms"] = round(t_, 3)
+                    extra[f"{key}_wino{ln_}_bit_exact"] = bool(torch.equal(Z, Z0))
+                    del Z
+                del Z0
+            del X, Y
+            torch.cuda.empty_cache()
+        # the factorisation variants of Sections 3.1 and 4.1 on the 8192
+        # uniform input: tile-iterative right-looking / Crout / left-looking
+        # (tiles of 512 and 1024), slab-recursive, against the tile recursion
+        log("[bench] factorisation variants at 8192 ...")
+        B0 = torch.from_numpy(wl.make("pluq8192_p131071")).to(dev)
+        ref_t, _, ref_o = pluq_on("pluq8192_p131071", ffp.PATH_AUTO, reps=3, B0=B0)
+        extra["variants8192_tile_recursive_ms"] = round(ref_t, 3)
+        Bv = torch.empty_like(B0)
+        info = torch.empty(1, dtype=torch.int32, device=dev)
+        for vname, var in (("right", ffp.LU_RIGHT), ("crout", ffp.LU_CROUT), ("left", ffp.LU_LEFT)):
+            for kt in (512, 1024):
+                wsv = torch.empty(ffp.lu_tiled_workspace(var, 8192, 8192, kt, 131071), dtype=torch.uint8, device=dev)
+
+                def run_v():
+                    Bv.copy_(B0)
+                    ffp.lu_tiled(Bv, 131071, var, kt, info=info, ws=wsv)
+                t_, _ = timed(run_v, 3)
+                extra[f"variants8192_{vname}_k{kt}_ms"] = round(t_, 3)
+                extra[f"variants8192_{vname}_k{kt}_bit_exact"] = bool(torch.equal(Bv, ref_o[0])) and int(info) == 0
+                extra[f"variants8192_{vname}_k{kt}_model_reductions"] = ffp.reduction_count(var, 8192, kt)
+                del wsv
+        extra["variants8192_tile_recursive_model_reductions"] = ffp.reduction_count(ffp.LU_TILE_RECURSIVE, 8192)
+        extra["variants8192_slab_recursive_model_reductions"] = ffp.reduction_count(ffp.LU_SLAB_RECURSIVE, 8192)
+        for name in ("pluq8192_p131071", "pluq8192_r4096_p131071"):
+            S0 = torch.from_numpy(wl.make(name)).to(dev)
+            Sv = torch.empty_like(S0)
+            out_s = {}
+
+            def run_s():
+                Sv.copy_(S0)
+                out_s["r"] = ffp.pluq_slab(Sv, 131071)
+            t_, _ = timed(run_s, 2)
+            extra[f"{name}_slab_recursive_ms"] = round(t_, 3)
+            extra[f"{name}_slab_recursive_rank"] = out_s["r"].rank
+            del S0, Sv
+        del B0, Bv, ref_o
+        torch.cuda.empty_cache()
+        # echelon forms of the rank-4096 input from its factorisation
+        log("[bench] echelon forms ...")
+        E0 = torch.from_numpy(wl.make("pluq8192_r4096_p131071")).to(dev)
+        res_e = ffp.pluq(E0, 131071)
+        t_, _ = timed(lambda: ffp.echelon(res_e, 131071, form=0), 2)
+        extra["pluq8192_r4096_row_echelon_ms"] = round(t_, 3)
+        t_, _ = timed(lambda: ffp.nullspace(res_e, 131071, side=0), 2)
+        extra["pluq8192_r4096_nullspace_ms"] = round(t_, 3)
+        del E0, res_e
+        torch.cuda.empty_cache()
         # the batched persistent PLUQ on its own workload (4096 matrices,
         # m, n uniform in [16, 512], ranks uniform in [1, min]); ranks checked
         log("[bench] batched workload ...")
