@@ -270,8 +270,12 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
         __syncthreads();
         // ---- rank-one update of the active block, 32 rows at a time: all
         // loads of a half are issued before any of its stores
+        // every updated entry is reduced to (-p, p) on the spot, so that the
+        // nonzero-row masks of the walk come out of the update itself (the
+        // masks of rows outside the update are zero: they are done)
         const double uu = (cact && lane != y) ? u : 0.0;
         const uint64_t act = allr & ~rowdone & ~(1ull << x);
+        uint64_t mk = 0;
 #pragma unroll
         for (int g = 0; g < 64; g += 32) {
             if (!((act >> g) & 0xffffffffull)) continue;
@@ -282,7 +286,10 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
                 lv[q] = Lc[g + q];
             }
 #pragma unroll
-            for (int q = 0; q < 32; ++q) wv[q] = fma(-lv[q], uu, wv[q]);
+            for (int q = 0; q < 32; ++q) {
+                wv[q] = mod_near(fma(-lv[q], uu, wv[q]), p, pinv);
+                mk |= (uint64_t)(wv[q] != 0.0) << (g + q);
+            }
 #pragma unroll
             for (int q = 0; q < 32; ++q) W[g + q][lane] = wv[q];
         }
@@ -302,7 +309,8 @@ __global__ __launch_bounds__(64) void k_leaf64(int mb, int nb, int32_t *__restri
         rowdone |= 1ull << x;
         coldone |= 1ull << y;
         ++r;
-        nz_valid = false;
+        nzm = cact && lane != y ? (mk & act) : 0ull;
+        nz_valid = true;
         __syncthreads();
     }
 
