@@ -50,3 +50,23 @@ def test_full_size_outputs_equal_oracle(lib, name):
            "rrp": _digest(res.rrp.cpu().numpy()[:r]), "crp": _digest(res.crp.cpu().numpy()[:r])}
     for k, v in got.items():
         assert v == want[k], (name, k)
+
+
+@pytest.mark.parametrize("name", [x for x in _names() if x.startswith("pluq8192")])
+def test_full_size_fp64_path_equals_oracle(lib, name):
+    """The same 8192 workloads with every product forced onto the FP64 MFMA
+    path (the AUTO run takes INT8 limbs for the large products)."""
+    from paper_1402_3501_amd import PATH_FP64
+    import torch
+    want = json.load(open(DIGESTS))[name]
+    spec = wl.WORKLOADS[name]
+    A = torch.from_numpy(wl.make(name)).cuda()
+    note("golden fp64", name)
+    res = lib.pluq(A, spec["p"], path=PATH_FP64)
+    torch.cuda.synchronize()
+    r = res.rank
+    assert r == want["rank"]
+    got = {"LU": _digest(A.cpu().numpy()), "P": _digest(res.P.cpu().numpy()), "Q": _digest(res.Q.cpu().numpy()),
+           "rrp": _digest(res.rrp.cpu().numpy()[:r]), "crp": _digest(res.crp.cpu().numpy()[:r])}
+    for k, v in got.items():
+        assert v == want[k], (name, k)

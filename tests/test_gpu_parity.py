@@ -107,6 +107,55 @@ def test_fgemm_long_k_reductions(lib, orc):
         assert np.array_equal(host(Cd), want)
 
 
+@pytest.mark.parametrize("p", [251, 65521, 8388593])
+def test_fgemm_int8_k_chunks(lib, orc, p):
+    """INT8 products whose k exceeds one chunk of the INT8 path (the int32
+    shift-class accumulators are reduced mod p after every chunk: 131072
+    products with one limb, 65536 with two, 32768 with three), so a later
+    chunk adds onto the reduced result of the earlier ones with its operands
+    read at the chunk's offset; alpha, beta and transposed operands."""
+    from paper_1402_3501_amd import PATH_INT8, int8_limbs
+    L = int8_limbs(p)
+    chunk = {1: 131072, 2: 65536, 3: 32768}[L]
+    rng = np.random.default_rng(p + 11)
+    m, n, k = 64, 48, chunk + 232
+    for ta, tb in [(0, 0), (1, 1)]:
+        A = rng.integers(0, p, (k, m) if ta else (m, k)).astype(np.int32)
+        B = rng.integers(0, p, (n, k) if tb else (k, n)).astype(np.int32)
+        C = rng.integers(0, p, (m, n)).astype(np.int32)
+        alpha, beta = int(rng.integers(1, p)), int(rng.integers(1, p))
+        note("fgemm int8 k chunks", p, L, m, n, k, ta, tb, alpha, beta)
+        want = orc.fgemm(A, B, C, p, alpha, beta, bool(ta), bool(tb))
+        Cd = dev(C)
+        lib.fgemm(dev(A), dev(B), Cd, p, alpha, beta, bool(ta), bool(tb), path=PATH_INT8)
+        assert np.array_equal(host(Cd), want), (p, ta, tb)
+
+
+@pytest.mark.parametrize("p", [131071, 94906249])
+def test_fgemm_f64_large_tiles_transposed(lib, orc, p):
+    """FP64 products large enough for the 128 x 128 tile kernel (at least 192
+    output tiles of 128), with every transpose combination, ragged edges on
+    all three dimensions and, for p = 94906249, reductions inside the K loop;
+    40 sampled rows (plus the first and last) checked against the oracle."""
+    from paper_1402_3501_amd import PATH_FP64
+    rng = np.random.default_rng(p + 13)
+    m, n, k = 2000, 1700, 333
+    assert ((m + 127) // 128) * ((n + 127) // 128) >= 192
+    rows = np.unique(np.concatenate([[0, m - 1], rng.choice(m, 40, replace=False)]))
+    for ta, tb in [(0, 0), (1, 0), (0, 1), (1, 1)]:
+        A = rng.integers(0, p, (k, m) if ta else (m, k)).astype(np.int32)
+        B = rng.integers(0, p, (n, k) if tb else (k, n)).astype(np.int32)
+        C = rng.integers(0, p, (m, n)).astype(np.int32)
+        alpha, beta = int(rng.integers(1, p)), int(rng.integers(1, p))
+        note("fgemm f64 128-tiles", p, m, n, k, ta, tb)
+        Cd = dev(C)
+        lib.fgemm(dev(A), dev(B), Cd, p, alpha, beta, bool(ta), bool(tb), path=PATH_FP64)
+        got = host(Cd)
+        As = np.ascontiguousarray(A[:, rows] if ta else A[rows])
+        want = orc.fgemm(As, B, np.ascontiguousarray(C[rows]), p, alpha, beta, bool(ta), bool(tb))
+        assert np.array_equal(got[rows], want), (p, ta, tb)
+
+
 def test_fgemm_submatrix_views(lib, orc):
     """Operands as strided views (leading dimension > columns, unaligned offsets)."""
     import torch
