@@ -340,17 +340,30 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 bwalk_w(S, nwr, nwc, ln);
             } else {
-                // the pivot column's final L entries, kept as pending column np
+                // the pivot column's final L entries, kept as pending column np:
+                // each thread's rows are read and corrected first, so that the
+                // pivot's inverse is computed while those loads are in flight
+                constexpr int LR = (kBMax + kBT - 65) / (kBT - 64);  // rows per thread
+                double sv[LR];
+#pragma unroll
+                for (int e = 0; e < LR; ++e) {
+                    const int i = tid - 64 + e * (kBT - 64);
+                    sv[e] = (i < m && i != x && !bbit(S.rowdone, i))
+                                ? schur_val(W[(int64_t)i * n + y], Lb + i * nb, Ub + y, ldu, np, kred, p, pinv)
+                                : 0.0;
+                }
                 const int32_t piv = S.upiv;
                 const double inv =
                     (double)(p < 16777216.0 ? inv_mod_small(piv, (int32_t)p) : inv_mod(piv, (int32_t)p));
-                for (int i = tid - 64; i < m; i += kBT - 64)
-                    if (i != x && !bbit(S.rowdone, i)) {
-                        const double s = schur_val(W[(int64_t)i * n + y], Lb + i * nb, Ub + y, ldu, np, kred, p, pinv);
-                        const double l = mod_canon(s * inv, p, pinv);
+#pragma unroll
+                for (int e = 0; e < LR; ++e) {
+                    const int i = tid - 64 + e * (kBT - 64);
+                    if (i < m && i != x && !bbit(S.rowdone, i)) {
+                        const double l = mod_canon(sv[e] * inv, p, pinv);
                         W[(int64_t)i * n + y] = (int32_t)l;
                         Lb[i * nb + np] = (int32_t)centre((int32_t)l, p, half);
                     }
+                }
             }
             __syncthreads();
             }
@@ -397,38 +410,74 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
                 __syncthreads();
             }
             {
+                // each wave takes RB listed rows at a time and CH chunks of 64
+                // listed columns: RB x CH loads in flight per lane, and every
+                // pending entry read from LDS serves RB (U) or CH (L) updates.
+                // Per entry the same fma chain as schur_val, so the same bits.
                 const int nrl = S.nrl, ncl = S.ncl;
-                constexpr int CH = 4;
+                constexpr int CH = 4, RB = kBT >= 1024 ? 2 : 4;
                 const int nch = (ncl + 63) >> 6;
-                for (int q = wv; q < nrl; q += NWV) {
-                    const int i = S.rl[q];
-                    const int32_t *Lr = Lb + i * nb;
-                    bool nzr = false;
+                for (int q0 = wv * RB; q0 < nrl; q0 += NWV * RB) {
+                    int ii[RB];
+                    bool rok[RB], nzr[RB];
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+                        rok[rb] = q0 + rb < nrl;
+                        ii[rb] = S.rl[rok[rb] ? q0 + rb : q0];
+                        nzr[rb] = false;
+                    }
                     for (int ch0 = 0; ch0 < nch; ch0 += CH) {
                         int col[CH];
                         bool ok[CH];
-                        int32_t v[CH];
 #pragma unroll
                         for (int cc = 0; cc < CH; ++cc) {
                             const int qq = ln + 64 * (ch0 + cc);
                             ok[cc] = qq < ncl;
                             col[cc] = S.cl[ok[cc] ? qq : ncl - 1];
                         }
+                        double a[RB][CH];
 #pragma unroll
-                        for (int cc = 0; cc < CH; ++cc) v[cc] = W[(int64_t)i * n + col[cc]];
+                        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                        for (int cc = 0; cc < CH; ++cc) {
-                            if (!ok[cc]) continue;
-                            const int32_t nv = (int32_t)schur_val(v[cc], Lr, Ub + col[cc], ldu, npf, kred, p, pinv);
-                            W[(int64_t)i * n + col[cc]] = nv;
-                            nzr |= nv != 0;
+                            for (int cc = 0; cc < CH; ++cc) a[rb][cc] = (double)W[(int64_t)ii[rb] * n + col[cc]];
+                        int k = 0;
+                        for (int t = 0; t < npf; ++t) {
+                            double u[CH], l[RB];
+#pragma unroll
+                            for (int cc = 0; cc < CH; ++cc) u[cc] = (double)Ub[t * ldu + col[cc]];
+#pragma unroll
+                            for (int rb = 0; rb < RB; ++rb) l[rb] = (double)Lb[ii[rb] * nb + t];
+#pragma unroll
+                            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                                for (int cc = 0; cc < CH; ++cc) a[rb][cc] = fma(-l[rb], u[cc], a[rb][cc]);
+                            if (++k == kred) {
+#pragma unroll
+                                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                                    for (int cc = 0; cc < CH; ++cc) a[rb][cc] = mod_near(a[rb][cc], p, pinv);
+                                k = 0;
+                            }
                         }
+#pragma unroll
+                        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                            for (int cc = 0; cc < CH; ++cc)
+                                if (rok[rb] && ok[cc]) {
+                                    const int32_t nv = (int32_t)mod_canon(a[rb][cc], p, pinv);
+                                    W[(int64_t)ii[rb] * n + col[cc]] = nv;
+                                    nzr[rb] |= nv != 0;
+                                }
                     }
                     // a listed row's active entries are the listed columns
-                    const bool any = __ballot(nzr) != 0ull;
-                    if (ln == 0) {
-                        if (any) atomicOr(&S.nz[i >> 5], 1u << (i & 31));
-                        else atomicAnd(&S.nz[i >> 5], ~(1u << (i & 31)));
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+                        const bool any = __ballot(nzr[rb]) != 0ull;
+                        if (ln == 0 && rok[rb]) {
+                            const int i = ii[rb];
+                            if (any) atomicOr(&S.nz[i >> 5], 1u << (i & 31));
+                            else atomicAnd(&S.nz[i >> 5], ~(1u << (i & 31)));
+                        }
                     }
                 }
             }
