@@ -188,9 +188,10 @@ __global__ __launch_bounds__(1024) void k_batch_order(int32_t batch, const int32
 // Current Schur-complement value of an entry whose stored value w has not
 // yet received the np pending pivots: w - sum_t L[t] U[t] (L: the row's
 // pending multipliers, U: the pending pivot rows at the entry's column,
-// stride ldu; both centred), exact in FP64 with a reduction every kred terms;
-// canonical result.
-__device__ __forceinline__ double schur_val(int32_t w, const int32_t *L, const int32_t *U, int ldu, int np, int kred,
+// stride ldu; both centred, held as PT: int16_t when p < 2^16, else int32_t),
+// exact in FP64 with a reduction every kred terms; canonical result.
+template <typename PT>
+__device__ __forceinline__ double schur_val(int32_t w, const PT *L, const PT *U, int ldu, int np, int kred,
                                             double p, double pinv) {
     double acc = (double)w;
     int k = 0;
@@ -212,7 +213,7 @@ __device__ __forceinline__ int wprefix(bool f, int lane, int *tot) {
     return __popcll(b & ((lane ? (~0ull >> (64 - lane)) : 0ull)));
 }
 
-template <int kBT>
+template <int kBT, typename PT>
 __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32_t *__restrict__ m_arr,
                                                       const int32_t *__restrict__ n_arr, int32_t *__restrict__ A,
                                                       const int64_t *__restrict__ A_off, int32_t *__restrict__ P,
@@ -226,8 +227,8 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
     __shared__ BShared S;
     // pending pivots (delayed rank-one updates): L[i][t] at Lb[i nb + t],
     // U[t][j] at Ub[t ldu + j], centred residues
-    extern __shared__ int32_t pend[];
-    int32_t *Lb = pend, *Ub = pend + (size_t)max_m * nb;
+    extern __shared__ __attribute__((aligned(16))) int32_t pend[];
+    PT *Lb = (PT *)pend, *Ub = Lb + (size_t)max_m * nb;
     const int ldu = max_n > 0 ? max_n : 1;
     const int tid = threadIdx.x;
     int32_t *W = slots + (int64_t)blockIdx.x * slot_elems;
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
                     const double u = schur_val(W[(int64_t)x * n + c], Lb + x * nb, Ub + c, ldu, np, kred, p, pinv);
                     if (c == y) S.upiv = (int32_t)u;
                     W[(int64_t)x * n + c] = (int32_t)u;
-                    Ub[np * ldu + c] = (int32_t)centre((int32_t)u, p, half);
+                    Ub[np * ldu + c] = (PT)centre((int32_t)u, p, half);
                 }
             __syncthreads();
             if (wv == 0) {
@@ -361,7 +362,7 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
                     if (i < m && i != x && !bbit(S.rowdone, i)) {
                         const double l = mod_canon(sv[e] * inv, p, pinv);
                         W[(int64_t)i * n + y] = (int32_t)l;
-                        Lb[i * nb + np] = (int32_t)centre((int32_t)l, p, half);
+                        Lb[i * nb + np] = (PT)centre((int32_t)l, p, half);
                     }
                 }
             }
@@ -607,10 +608,12 @@ static int launch_shape(int shape, const Field &F, int32_t batch, const int32_t 
     int32_t *slots = (int32_t *)ws.take((size_t)grid * (size_t)slot * 4);
     if (!counter || !order || !slots) return FFP_E_WORKSPACE;
     // pending-pivot buffers in LDS: as many pivots as the shape's share of
-    // the compute unit's 160 KiB leaves room for (at most 16)
+    // the compute unit's 160 KiB leaves room for (at most 16, or 32 with
+    // 16-bit entries: centred residues of p < 2^16 fit an int16_t)
+    const bool narrow = F.p < 65536u;
     const int64_t budget = (int64_t)(160 * 1024) / kShapes[shape].per_cu - (int64_t)sizeof(BShared) - 1024;
-    const int64_t per = 4 * (int64_t)((max_m > 0 ? max_m : 1) + (max_n > 0 ? max_n : 1));
-    int nb = (int)std::min<int64_t>(16, budget / per);
+    const int64_t per = (narrow ? 2 : 4) * (int64_t)((max_m > 0 ? max_m : 1) + (max_n > 0 ? max_n : 1));
+    int nb = (int)std::min<int64_t>(narrow ? 32 : 16, budget / per);
     if (nb < 1) nb = 1;
     const int kred = (int)std::min<int64_t>(nb, F.kexact > 0 ? F.kexact : 1);
     const size_t dyn = (size_t)nb * (size_t)per;
@@ -618,13 +621,19 @@ static int launch_shape(int shape, const Field &F, int32_t batch, const int32_t 
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, counter);
     hipLaunchKernelGGL(k_batch_order, dim3(1), dim3(1024), 0, s, batch, m_arr, n_arr, order);
     ProfScope prof(PK_BATCHED, 0.0, s, 0.0);
-#define FFP_BAT(T_)                                                                                            \
-    hipLaunchKernelGGL((k_pluq_batched<T_>), dim3(grid), dim3(T_), dyn, s, batch, m_arr, n_arr, A, A_off, P, P_off, \
+#define FFP_BAT(T_, PT_)                                                                                         \
+    hipLaunchKernelGGL((k_pluq_batched<T_, PT_>), dim3(grid), dim3(T_), dyn, s, batch, m_arr, n_arr, A, A_off, P, P_off, \
                        Q, Q_off, rank, rrp, crp, counter, order, slots, slot, max_m, max_n, F.pd, F.pinv,        \
                        (int32_t)F.half, nb, kred)
-    if (kShapes[shape].threads == 1024) FFP_BAT(1024);
-    else if (kShapes[shape].threads == 512) FFP_BAT(512);
-    else FFP_BAT(256);
+    if (narrow) {
+        if (kShapes[shape].threads == 1024) FFP_BAT(1024, int16_t);
+        else if (kShapes[shape].threads == 512) FFP_BAT(512, int16_t);
+        else FFP_BAT(256, int16_t);
+    } else {
+        if (kShapes[shape].threads == 1024) FFP_BAT(1024, int32_t);
+        else if (kShapes[shape].threads == 512) FFP_BAT(512, int32_t);
+        else FFP_BAT(256, int32_t);
+    }
 #undef FFP_BAT
     FFP_HIP_CHECK(hipGetLastError());
     ws.release(mk);
