@@ -60,20 +60,35 @@ __device__ __forceinline__ bool bbit(const uint32_t *m, int i) { return (m[i >> 
 // nonzero in the active columns hold no pivot and are skipped whole (S.nz);
 // this only prunes the walk, the regions that are visited and their order
 // are those of the recursion.  Called by all 64 lanes of wave 0.
+// The masks have at most kBW <= 32 words, held by lanes 0..31 (two DPP rows
+// of 16 lanes; the other lanes hold zeros), so sums and scans run within
+// the rows on DPP lane moves (a few cycles each) and join the two rows by
+// lane reads, rather than through LDS-routed shuffles.
+static_assert(kBW <= 32, "mask words fit two DPP rows of 16 lanes");
+constexpr int kDppRowShr = 0x110, kDppRowRor = 0x120;  // + shift 1..15
+template <int CTRL>
+__device__ __forceinline__ int dpp_move(int v) {
+    // lanes whose source lies outside the row read 0
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, true);
+}
+// sum over lanes 0..31, the same value returned to every lane
 __device__ __forceinline__ int wsum(int v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    return v;
+    v += dpp_move<kDppRowRor + 8>(v);
+    v += dpp_move<kDppRowRor + 4>(v);
+    v += dpp_move<kDppRowRor + 2>(v);
+    v += dpp_move<kDppRowRor + 1>(v);
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16);
 }
 // the k lowest set bits of the wave-distributed mask x (k <= popcount)
 __device__ __forceinline__ uint32_t wfirst_k(uint32_t x, int k, int lane) {
     const int c = __popc(x);
-    int incl = c;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int o = __shfl_up(incl, off);
-        if (lane >= off) incl += o;
-    }
+    int incl = c;  // inclusive prefix sum of the words' popcounts over lanes 0..31
+    incl += dpp_move<kDppRowShr + 1>(incl);
+    incl += dpp_move<kDppRowShr + 2>(incl);
+    incl += dpp_move<kDppRowShr + 4>(incl);
+    incl += dpp_move<kDppRowShr + 8>(incl);
+    const int row0 = __builtin_amdgcn_readlane(incl, 15);
+    if (lane >= 16 && lane < 32) incl += row0;
     const int excl = incl - c;
     if (incl <= k) return x;
     if (excl >= k) return 0u;
@@ -89,7 +104,7 @@ __device__ __forceinline__ uint32_t wfirst_k(uint32_t x, int k, int lane) {
 __device__ __forceinline__ int wfirst(uint32_t x) {
     const uint64_t b = __ballot(x != 0u);
     const int w = __ffsll((long long)b) - 1;
-    const uint32_t xw = (uint32_t)__shfl((int)x, w);
+    const uint32_t xw = (uint32_t)__builtin_amdgcn_readlane((int)x, w);
     return w * 32 + __ffs(xw) - 1;
 }
 
