@@ -30,6 +30,9 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kI8BM = 128, kI8BN = 128, kI8BK = 64;
 constexpr int kI8Threads = 512;
+// products whose grid of 128 x 128 blocks would not fill the chip run on
+// 64 x 64 blocks of four waves (two workgroups per compute unit)
+constexpr int kI8SmallB = 64, kI8SmallThreads = 256;
 // split-K: at most 4 parts, partial results at most 32 MiB
 constexpr int kI8MaxSplit = 4;
 constexpr int64_t kI8SplitBytes = (int64_t)32 << 20;
@@ -109,23 +112,25 @@ __global__ __launch_bounds__(256) void k_split(SplitSrc sa, SplitSrc sb, int64_t
 }
 
 // ------------------------------------------------------------------ product
-template <int L>
-__global__ __launch_bounds__(kI8Threads) void k_fgemm_i8(const int8_t *__restrict__ Ad, const int8_t *__restrict__ Bd,
+template <int L, int BM, int BN, int NT>
+__global__ __launch_bounds__(NT) void k_fgemm_i8(const int8_t *__restrict__ Ad, const int8_t *__restrict__ Bd,
                                                         int64_t Kp, int64_t planeA, int64_t planeB, int64_t m,
                                                         int64_t n, int32_t *__restrict__ C, int64_t ldc, double p,
                                                         double pinv, double alpha, double beta, double w1,
                                                         double w2, double w3, double w4, int ntx, int nty,
                                                         int64_t kt_per, int32_t *__restrict__ part) {
     constexpr int NS = 2 * L - 1;        // shift classes
-    constexpr int BM = kI8BM, BN = kI8BN, BK = kI8BK;
+    constexpr int BK = kI8BK;
     constexpr int ROW = BK + 16;         // padded LDS row (bytes)
-    constexpr int WM = 32, WN = 64;      // wave tile (8 waves: 4 x 2)
+    constexpr int WM = 32;               // wave tile rows; the waves form WGM x WGN
+    constexpr int WGM = BM / WM, WGN = NT / 64 / WGM, WN = BN / WGN;
+    static_assert(WGM * WGN * 64 == NT && WN % 16 == 0, "wave grid covers the block");
     constexpr int FM = WM / 16, FN = WN / 16;
     __shared__ __attribute__((aligned(16))) int8_t As[2][L][BM][ROW];
     __shared__ __attribute__((aligned(16))) int8_t Bs[2][L][BN][ROW];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
+    const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
     // part != nullptr: workgroup b computes K tiles [kt_per z, kt_per (z + 1))
     // of output block b % (ntx nty), z = b / (ntx nty), into part[z] (m x n)
     const int tiles = ntx * nty;
@@ -136,12 +141,12 @@ __global__ __launch_bounds__(kI8Threads) void k_fgemm_i8(const int8_t *__restric
 
     // global -> register staging: L*(BM+BN)*BK/16 chunks of 16 bytes
     constexpr int CH_A = L * BM * BK / 16, CH_B = L * BN * BK / 16;
-    constexpr int PER = (CH_A + CH_B + kI8Threads - 1) / kI8Threads;
+    constexpr int PER = (CH_A + CH_B + NT - 1) / NT;
     v4i stage[PER];
     auto load = [&](int64_t k0) {
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-            const int c = tid + e * kI8Threads;
+            const int c = tid + e * NT;
             if (c < CH_A) {
                 const int d = c / (BM * 4), rem = c % (BM * 4), row = rem >> 2, q = rem & 3;
                 stage[e] = *(const v4i *)(Ad + d * planeA + (m0 + row) * Kp + k0 + q * 16);
@@ -155,7 +160,7 @@ __global__ __launch_bounds__(kI8Threads) void k_fgemm_i8(const int8_t *__restric
     auto store = [&](int buf) {
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-            const int c = tid + e * kI8Threads;
+            const int c = tid + e * NT;
             if (c < CH_A) {
                 const int d = c / (BM * 4), rem = c % (BM * 4), row = rem >> 2, q = rem & 3;
                 *(v4i *)&As[buf][d][row][q * 16] = stage[e];
@@ -242,7 +247,7 @@ __global__ __launch_bounds__(kI8Threads) void k_fgemm_i8(const int8_t *__restric
 
 // C <- alpha * (sum of the nz partial results) + beta * C, all mod p (each
 // partial is canonical, the sum of at most kI8MaxSplit of them is exact);
-// row gi = blockIdx.y (split products have at most 128 blocks of 128 rows)
+// row gi = blockIdx.y (only products of at most 65535 rows are split)
 __global__ __launch_bounds__(256) void k_i8_combine(int64_t m, int64_t n, int nz, const int32_t *__restrict__ part,
                                                     int32_t *__restrict__ C, int64_t ldc, double p, double pinv,
                                                     double alpha, double beta) {
@@ -326,7 +331,12 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
                                sa, sb, Mp / 64, kc, Kp, (int32_t)F.half, (int32_t)F.p);
         }
         const double be = kc0 == 0 ? (double)beta : 1.0;
-        const int ntx = (int)(Np / kI8BN), nty = (int)(Mp / kI8BM);
+        // 128 x 128 blocks when they fill the chip's 256 compute units, else
+        // 64 x 64 blocks (measured on MI355X: 1024^3 with three limbs 31 us
+        // against 36 us, the 16384 factorisation 34.3 against 35.0 ms)
+        const bool small = (Np / kI8BN) * (Mp / kI8BM) < 256;
+        const int bs = small ? kI8SmallB : kI8BM;
+        const int ntx = (int)(Np / bs), nty = (int)(Mp / bs);
         const int64_t nt = Kp / kI8BK;
         int nz = i8_split((int64_t)ntx * nty, nt, m, n);
         int64_t kt_per = (nt + nz - 1) / nz;
@@ -347,9 +357,15 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
             ProfScope prof(PK_FGEMM_I8, 2.0 * (double)m * (double)n * (double)kc, s,
                            (double)L * ((double)m * (double)kc + (double)kc * (double)n) +
                                4.0 * (part ? (double)nz : (be != 0.0 ? 2.0 : 1.0)) * (double)m * (double)n);
-            hipLaunchKernelGGL((k_fgemm_i8<L>), dim3((unsigned)(ntx * nty * nz)), dim3(kI8Threads), 0, s, Ad, Bd, Kp,
-                               planeA, planeB, m, n, C, ldc, F.pd, F.pinv, (double)alpha, be, wts[0], wts[1],
-                               wts[2], wts[3], ntx, nty, kt_per, part);
+            if (small)
+                hipLaunchKernelGGL((k_fgemm_i8<L, kI8SmallB, kI8SmallB, kI8SmallThreads>),
+                                   dim3((unsigned)(ntx * nty * nz)), dim3(kI8SmallThreads), 0, s, Ad, Bd, Kp, planeA,
+                                   planeB, m, n, C, ldc, F.pd, F.pinv, (double)alpha, be, wts[0], wts[1], wts[2],
+                                   wts[3], ntx, nty, kt_per, part);
+            else
+                hipLaunchKernelGGL((k_fgemm_i8<L, kI8BM, kI8BN, kI8Threads>), dim3((unsigned)(ntx * nty * nz)),
+                                   dim3(kI8Threads), 0, s, Ad, Bd, Kp, planeA, planeB, m, n, C, ldc, F.pd, F.pinv,
+                                   (double)alpha, be, wts[0], wts[1], wts[2], wts[3], ntx, nty, kt_per, part);
         }
         if (part) {
             ProfScope prof(PK_I8_COMBINE, 0.0, s, 4.0 * ((double)nz + (be != 0.0 ? 2.0 : 1.0)) * (double)m * (double)n);
