@@ -17,6 +17,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 #include "ffp_internal.hpp"
 #include "ffp_device.hpp"
@@ -228,7 +229,10 @@ __device__ __forceinline__ int wprefix(bool f, int lane, int *tot) {
     return __popcll(b & ((lane ? (~0ull >> (64 - lane)) : 0ull)));
 }
 
-template <int kBT, typename PT>
+// NARROW (p < 2^16): the working copy holds canonical residues as uint16_t
+// and the pending pivots centred ones as int16_t, halving their bytes;
+// otherwise both are int32_t.
+template <int kBT, bool NARROW>
 __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32_t *__restrict__ m_arr,
                                                       const int32_t *__restrict__ n_arr, int32_t *__restrict__ A,
                                                       const int64_t *__restrict__ A_off, int32_t *__restrict__ P,
@@ -242,11 +246,13 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
     __shared__ BShared S;
     // pending pivots (delayed rank-one updates): L[i][t] at Lb[i nb + t],
     // U[t][j] at Ub[t ldu + j], centred residues
+    using PT = typename std::conditional<NARROW, int16_t, int32_t>::type;
+    using WT = typename std::conditional<NARROW, uint16_t, int32_t>::type;
     extern __shared__ __attribute__((aligned(16))) int32_t pend[];
     PT *Lb = (PT *)pend, *Ub = Lb + (size_t)max_m * nb;
     const int ldu = max_n > 0 ? max_n : 1;
     const int tid = threadIdx.x;
-    int32_t *W = slots + (int64_t)blockIdx.x * slot_elems;
+    WT *W = (WT *)slots + (int64_t)blockIdx.x * slot_elems;
     while (true) {
         if (tid == 0) {
             const int t = atomicAdd(counter, 1);
@@ -274,7 +280,7 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
                 bool any = false;
                 for (int c = ln; c < n; c += 64) {
                     const int32_t v = Aj[(int64_t)i * n + c];
-                    W[(int64_t)i * n + c] = v;
+                    W[(int64_t)i * n + c] = (WT)v;
                     any |= v != 0;
                 }
                 if (__ballot(any) != 0ull && ln == 0) atomicOr(&S.nz[i >> 5], 1u << (i & 31));
@@ -336,7 +342,7 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
                 if (!bbit(S.coldone, c)) {
                     const double u = schur_val(W[(int64_t)x * n + c], Lb + x * nb, Ub + c, ldu, np, kred, p, pinv);
                     if (c == y) S.upiv = (int32_t)u;
-                    W[(int64_t)x * n + c] = (int32_t)u;
+                    W[(int64_t)x * n + c] = (WT)u;
                     Ub[np * ldu + c] = (PT)centre((int32_t)u, p, half);
                 }
             __syncthreads();
@@ -376,7 +382,7 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
                     const int i = tid - 64 + e * (kBT - 64);
                     if (i < m && i != x && !bbit(S.rowdone, i)) {
                         const double l = mod_canon(sv[e] * inv, p, pinv);
-                        W[(int64_t)i * n + y] = (int32_t)l;
+                        W[(int64_t)i * n + y] = (WT)l;
                         Lb[i * nb + np] = (PT)centre((int32_t)l, p, half);
                     }
                 }
@@ -481,7 +487,7 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
                             for (int cc = 0; cc < CH; ++cc)
                                 if (rok[rb] && ok[cc]) {
                                     const int32_t nv = (int32_t)mod_canon(a[rb][cc], p, pinv);
-                                    W[(int64_t)ii[rb] * n + col[cc]] = nv;
+                                    W[(int64_t)ii[rb] * n + col[cc]] = (WT)nv;
                                     nzr[rb] |= nv != 0;
                                 }
                     }
@@ -546,7 +552,7 @@ __global__ __launch_bounds__(kBT) void k_pluq_batched(int32_t batch, const int32
         for (int64_t e = tid; e < (int64_t)m * n; e += kBT) {
             const int i = (int)(e / n), c = (int)(e % n);
             const bool keep = bbit(S.rowdone, i) || bbit(S.coldone, c);
-            Aj[(int64_t)S.rord[i] * n + S.cord[c]] = keep ? W[e] : 0;
+            Aj[(int64_t)S.rord[i] * n + S.cord[c]] = keep ? (int32_t)W[e] : 0;
         }
         int32_t *Pj = P + P_off[job], *Qj = Q + Q_off[job];
         for (int i = tid; i < m; i += kBT) Pj[S.rord[i]] = i;
@@ -641,13 +647,13 @@ static int launch_shape(int shape, const Field &F, int32_t batch, const int32_t 
                        Q, Q_off, rank, rrp, crp, counter, order, slots, slot, max_m, max_n, F.pd, F.pinv,        \
                        (int32_t)F.half, nb, kred)
     if (narrow) {
-        if (kShapes[shape].threads == 1024) FFP_BAT(1024, int16_t);
-        else if (kShapes[shape].threads == 512) FFP_BAT(512, int16_t);
-        else FFP_BAT(256, int16_t);
+        if (kShapes[shape].threads == 1024) FFP_BAT(1024, true);
+        else if (kShapes[shape].threads == 512) FFP_BAT(512, true);
+        else FFP_BAT(256, true);
     } else {
-        if (kShapes[shape].threads == 1024) FFP_BAT(1024, int32_t);
-        else if (kShapes[shape].threads == 512) FFP_BAT(512, int32_t);
-        else FFP_BAT(256, int32_t);
+        if (kShapes[shape].threads == 1024) FFP_BAT(1024, false);
+        else if (kShapes[shape].threads == 512) FFP_BAT(512, false);
+        else FFP_BAT(256, false);
     }
 #undef FFP_BAT
     FFP_HIP_CHECK(hipGetLastError());
