@@ -80,6 +80,26 @@ def test_batched_edge_shapes(lib, orc):
     _compare(orc, ms, ns, A, off, p, out, range(len(shapes)))
 
 
+@pytest.mark.parametrize("p", [65521, 131071])
+def test_batched_maximum_dimensions(lib, orc, p):
+    """Matrices at the largest dimension the batched call takes (1024 rows or
+    columns: 32 mask words, both halves of the walk's lane reductions), on
+    the 16-bit (p < 2^16) and the 32-bit working copies, with full, partial
+    and unit rank and a thin block beside them."""
+    FFP_BATCH_MAX_DIM = 1024
+    shapes = [(FFP_BATCH_MAX_DIM, FFP_BATCH_MAX_DIM, 700), (FFP_BATCH_MAX_DIM, 1000, 1000),
+              (999, FFP_BATCH_MAX_DIM, 1), (FFP_BATCH_MAX_DIM, 3, 3), (5, FFP_BATCH_MAX_DIM, 5)]
+    mats = [wl.lowrank(m, n, r, p, 7 * m + n) for (m, n, r) in shapes]
+    ms = np.array([s[0] for s in shapes])
+    ns = np.array([s[1] for s in shapes])
+    off = np.concatenate([[0], np.cumsum(ms * ns)[:-1]]).astype(np.int64)
+    A = np.concatenate([x.ravel() for x in mats]).astype(np.int32)
+    note("batched maximum dimensions", p)
+    out = _run(lib, ms, ns, A, off, p)
+    assert np.array_equal(out[3][:len(ms)], [s[2] for s in shapes])
+    _compare(orc, ms, ns, A, off, p, out, range(len(shapes)))
+
+
 def test_batched_workload_4096(lib, orc):
     """The 4096-matrix workload (m, n uniform in [16, 512], rank uniform in
     [1, min]): every rank equals the constructed one, a sample of matrices is
