@@ -33,6 +33,10 @@ constexpr int kI8Threads = 512;
 // products whose grid of 128 x 128 blocks would not fill the chip run on
 // 64 x 64 blocks of four waves (two workgroups per compute unit)
 constexpr int kI8SmallB = 64, kI8SmallThreads = 256;
+// one limb (one accumulator set) leaves the registers for 256 x 256 blocks of
+// eight waves with 64 x 128 wave tiles, 128 deep per barrier: eight times
+// the products per barrier, and twice the time to hide the next tile's loads
+constexpr int kI8WideB = 256, kI8WideBK = 128;
 // split-K: at most 4 parts, partial results at most 32 MiB
 constexpr int kI8MaxSplit = 4;
 constexpr int64_t kI8SplitBytes = (int64_t)32 << 20;
@@ -112,7 +116,7 @@ __global__ __launch_bounds__(256) void k_split(SplitSrc sa, SplitSrc sb, int64_t
 }
 
 // ------------------------------------------------------------------ product
-template <int L, int BM, int BN, int NT>
+template <int L, int BM, int BN, int NT, int WM, int BK>
 __global__ __launch_bounds__(NT) void k_fgemm_i8(const int8_t *__restrict__ Ad, const int8_t *__restrict__ Bd,
                                                         int64_t Kp, int64_t planeA, int64_t planeB, int64_t m,
                                                         int64_t n, int32_t *__restrict__ C, int64_t ldc, double p,
@@ -120,9 +124,9 @@ __global__ __launch_bounds__(NT) void k_fgemm_i8(const int8_t *__restrict__ Ad, 
                                                         double w2, double w3, double w4, int ntx, int nty,
                                                         int64_t kt_per, int32_t *__restrict__ part) {
     constexpr int NS = 2 * L - 1;        // shift classes
-    constexpr int BK = kI8BK;
     constexpr int ROW = BK + 16;         // padded LDS row (bytes)
-    constexpr int WM = 32;               // wave tile rows; the waves form WGM x WGN
+    constexpr int QR = BK / 16;          // 16-byte chunks per row
+    // wave tiles of WM rows; the waves form WGM x WGN
     constexpr int WGM = BM / WM, WGN = NT / 64 / WGM, WN = BN / WGN;
     static_assert(WGM * WGN * 64 == NT && WN % 16 == 0, "wave grid covers the block");
     constexpr int FM = WM / 16, FN = WN / 16;
@@ -148,11 +152,11 @@ __global__ __launch_bounds__(NT) void k_fgemm_i8(const int8_t *__restrict__ Ad, 
         for (int e = 0; e < PER; ++e) {
             const int c = tid + e * NT;
             if (c < CH_A) {
-                const int d = c / (BM * 4), rem = c % (BM * 4), row = rem >> 2, q = rem & 3;
+                const int d = c / (BM * QR), rem = c % (BM * QR), row = rem / QR, q = rem % QR;
                 stage[e] = *(const v4i *)(Ad + d * planeA + (m0 + row) * Kp + k0 + q * 16);
             } else if (c < CH_A + CH_B) {
                 const int cb = c - CH_A;
-                const int d = cb / (BN * 4), rem = cb % (BN * 4), row = rem >> 2, q = rem & 3;
+                const int d = cb / (BN * QR), rem = cb % (BN * QR), row = rem / QR, q = rem % QR;
                 stage[e] = *(const v4i *)(Bd + d * planeB + (n0 + row) * Kp + k0 + q * 16);
             }
         }
@@ -162,11 +166,11 @@ __global__ __launch_bounds__(NT) void k_fgemm_i8(const int8_t *__restrict__ Ad, 
         for (int e = 0; e < PER; ++e) {
             const int c = tid + e * NT;
             if (c < CH_A) {
-                const int d = c / (BM * 4), rem = c % (BM * 4), row = rem >> 2, q = rem & 3;
+                const int d = c / (BM * QR), rem = c % (BM * QR), row = rem / QR, q = rem % QR;
                 *(v4i *)&As[buf][d][row][q * 16] = stage[e];
             } else if (c < CH_A + CH_B) {
                 const int cb = c - CH_A;
-                const int d = cb / (BN * 4), rem = cb % (BN * 4), row = rem >> 2, q = rem & 3;
+                const int d = cb / (BN * QR), rem = cb % (BN * QR), row = rem / QR, q = rem % QR;
                 *(v4i *)&Bs[buf][d][row][q * 16] = stage[e];
             }
         }
@@ -188,7 +192,10 @@ __global__ __launch_bounds__(NT) void k_fgemm_i8(const int8_t *__restrict__ Ad, 
     for (int64_t t = 0; t < nt; ++t) {
         const int buf = (int)(t & 1);
         if (t + 1 < nt) load((t0 + t + 1) * BK);
-        const int kq = (lane >> 4) * 16, r = lane & 15;
+        const int r = lane & 15;
+#pragma unroll
+        for (int h = 0; h < BK / 64; ++h) {
+        const int kq = (lane >> 4) * 16 + 64 * h;
         v4i a[L][FM];
 #pragma unroll
         for (int d = 0; d < L; ++d)
@@ -207,6 +214,7 @@ __global__ __launch_bounds__(NT) void k_fgemm_i8(const int8_t *__restrict__ Ad, 
                     for (int j = 0; j < FN; ++j)
                         acc[da + db][i][j] =
                             __builtin_amdgcn_mfma_i32_16x16x64_i8(a[da][i], b[j], acc[da + db][i][j], 0, 0, 0);
+        }
         }
         if (t + 1 < nt) store(buf ^ 1);
         __syncthreads();
@@ -270,11 +278,16 @@ __global__ __launch_bounds__(256) void k_i8_combine(int64_t m, int64_t n, int nz
 // ------------------------------------------------------------------ host side
 static int64_t kchunk_for(int L) { return L == 1 ? 131072 : (L == 2 ? 65536 : 32768); }
 
+// rows of the limb planes: zero-padded to whole blocks of the largest tile
+static int64_t plane_rows(int L, int64_t r) { return rup(r, L == 1 ? kI8WideB : kI8BM); }
+// and columns: zero-padded to whole K tiles of the deepest kernel
+static int64_t plane_k(int L) { return L == 1 ? kI8WideBK : kI8BK; }
+
 size_t fgemm_i8_ws(const Field &F, int64_t m, int64_t n, int64_t k) {
     const int L = F.limbs > 0 ? F.limbs : 3;
     const int64_t kc = k < kchunk_for(L) ? k : kchunk_for(L);
-    const int64_t Kp = rup(kc > 0 ? kc : 1, kI8BK);
-    return (size_t)L * (size_t)(rup(m, kI8BM) + rup(n, kI8BN)) * (size_t)Kp + 1024;
+    const int64_t Kp = rup(kc > 0 ? kc : 1, plane_k(L));
+    return (size_t)L * (size_t)(plane_rows(L, m) + plane_rows(L, n)) * (size_t)Kp + 1024;
 }
 
 // The split-K partial results are optional workspace: a product splits K
@@ -302,7 +315,7 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
                   const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta, int32_t *C,
                   int64_t ldc, Arena &ws, hipStream_t s) {
     const int64_t KC = kchunk_for(L);
-    const int64_t Mp = rup(m, kI8BM), Np = rup(n, kI8BN);
+    const int64_t Mp = plane_rows(L, m), Np = plane_rows(L, n);
     double wts[4] = {0, 0, 0, 0};
     {
         uint64_t x = 1;
@@ -313,7 +326,7 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
     }
     for (int64_t kc0 = 0; kc0 < k; kc0 += KC) {
         const int64_t kc = k - kc0 < KC ? k - kc0 : KC;
-        const int64_t Kp = rup(kc, kI8BK);
+        const int64_t Kp = rup(kc, plane_k(L));
         const size_t mk = ws.mark();
         const int64_t planeA = Mp * Kp, planeB = Np * Kp;
         int8_t *Ad = (int8_t *)ws.take((size_t)L * planeA);
@@ -333,10 +346,12 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
         const double be = kc0 == 0 ? (double)beta : 1.0;
         // 128 x 128 blocks when they fill the chip's 256 compute units, else
         // 64 x 64 blocks (measured on MI355X: 1024^3 with three limbs 31 us
-        // against 36 us, the 16384 factorisation 34.3 against 35.0 ms)
-        const bool small = (Np / kI8BN) * (Mp / kI8BM) < 256;
-        const int bs = small ? kI8SmallB : kI8BM;
-        const int ntx = (int)(Np / bs), nty = (int)(Mp / bs);
+        // against 36 us, the 16384 factorisation 34.3 against 35.0 ms); one
+        // limb takes 256 x 256 blocks whenever they fill the chip
+        const bool wide = L == 1 && (rup(n, kI8WideB) / kI8WideB) * (rup(m, kI8WideB) / kI8WideB) >= 256;
+        const bool small = !wide && (rup(n, kI8BN) / kI8BN) * (rup(m, kI8BM) / kI8BM) < 256;
+        const int bs = wide ? kI8WideB : (small ? kI8SmallB : kI8BM);
+        const int ntx = (int)(rup(n, bs) / bs), nty = (int)(rup(m, bs) / bs);
         const int64_t nt = Kp / kI8BK;
         int nz = i8_split((int64_t)ntx * nty, nt, m, n);
         int64_t kt_per = (nt + nz - 1) / nz;
@@ -357,13 +372,21 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
             ProfScope prof(PK_FGEMM_I8, 2.0 * (double)m * (double)n * (double)kc, s,
                            (double)L * ((double)m * (double)kc + (double)kc * (double)n) +
                                4.0 * (part ? (double)nz : (be != 0.0 ? 2.0 : 1.0)) * (double)m * (double)n);
-            if (small)
-                hipLaunchKernelGGL((k_fgemm_i8<L, kI8SmallB, kI8SmallB, kI8SmallThreads>),
+            if constexpr (L == 1) {
+                if (wide)
+                    hipLaunchKernelGGL((k_fgemm_i8<1, kI8WideB, kI8WideB, kI8Threads, 64, kI8WideBK>),
+                                       dim3((unsigned)(ntx * nty * nz)), dim3(kI8Threads), 0, s, Ad, Bd, Kp, planeA,
+                                       planeB, m, n, C, ldc, F.pd, F.pinv, (double)alpha, be, wts[0], wts[1], wts[2],
+                                       wts[3], ntx, nty, kt_per, part);
+            }
+            if (wide) {
+            } else if (small)
+                hipLaunchKernelGGL((k_fgemm_i8<L, kI8SmallB, kI8SmallB, kI8SmallThreads, 32, kI8BK>),
                                    dim3((unsigned)(ntx * nty * nz)), dim3(kI8SmallThreads), 0, s, Ad, Bd, Kp, planeA,
                                    planeB, m, n, C, ldc, F.pd, F.pinv, (double)alpha, be, wts[0], wts[1], wts[2],
                                    wts[3], ntx, nty, kt_per, part);
             else
-                hipLaunchKernelGGL((k_fgemm_i8<L, kI8BM, kI8BN, kI8Threads>), dim3((unsigned)(ntx * nty * nz)),
+                hipLaunchKernelGGL((k_fgemm_i8<L, kI8BM, kI8BN, kI8Threads, 32, kI8BK>), dim3((unsigned)(ntx * nty * nz)),
                                    dim3(kI8Threads), 0, s, Ad, Bd, Kp, planeA, planeB, m, n, C, ldc, F.pd, F.pinv,
                                    (double)alpha, be, wts[0], wts[1], wts[2], wts[3], ntx, nty, kt_per, part);
         }
