@@ -156,6 +156,78 @@ def test_fgemm_f64_large_tiles_transposed(lib, orc, p):
         assert np.array_equal(got[rows], want), (p, ta, tb)
 
 
+@pytest.mark.parametrize("p", [257, 32749])
+def test_fgemm_int8_two_limbs(lib, orc, p):
+    """Primes whose centred residues take two INT8 limbs (257 <= p <= 32749
+    here): three shift classes, on the 64 x 64 blocks (with and without
+    split K) and on the 128 x 128 blocks (sampled rows), all transposes."""
+    from paper_1402_3501_amd import PATH_INT8, int8_limbs
+    assert int8_limbs(p) == 2
+    rng = np.random.default_rng(p + 17)
+    for (m, n, k) in [(7, 5, 3), (130, 70, 333), (150, 260, 2000)]:
+        for ta, tb in [(0, 0), (1, 0), (0, 1), (1, 1)]:
+            A = rng.integers(0, p, (k, m) if ta else (m, k)).astype(np.int32)
+            B = rng.integers(0, p, (n, k) if tb else (k, n)).astype(np.int32)
+            C = rng.integers(0, p, (m, n)).astype(np.int32)
+            alpha, beta = int(rng.integers(1, p)), int(rng.integers(0, p))
+            note("fgemm two limbs", p, m, n, k, ta, tb)
+            want = orc.fgemm(A, B, C, p, alpha, beta, bool(ta), bool(tb))
+            Cd = dev(C)
+            lib.fgemm(dev(A), dev(B), Cd, p, alpha, beta, bool(ta), bool(tb), path=PATH_INT8)
+            assert np.array_equal(host(Cd), want), (p, m, n, k, ta, tb)
+    m, n, k = 2100, 2050, 300  # 17 x 17 blocks of 128
+    A = rng.integers(0, p, (m, k)).astype(np.int32)
+    B = rng.integers(0, p, (k, n)).astype(np.int32)
+    C = rng.integers(0, p, (m, n)).astype(np.int32)
+    note("fgemm two limbs, 128 blocks", p)
+    Cd = dev(C)
+    lib.fgemm(dev(A), dev(B), Cd, p, 3, 5, path=PATH_INT8)
+    got = host(Cd)
+    rows = np.unique(np.concatenate([[0, m - 1], rng.choice(m, 40, replace=False)]))
+    want = orc.fgemm(np.ascontiguousarray(A[rows]), B, np.ascontiguousarray(C[rows]), p, 3, 5)
+    assert np.array_equal(got[rows], want)
+
+
+def test_fgemm_int8_one_limb_wide_blocks(lib, orc):
+    """One-limb products large enough for the 256 x 256 blocks (at least 256
+    of them), with ragged edges in both dimensions, K not a multiple of the
+    128-deep K tile, every transpose combination, alpha and beta; 40 sampled
+    rows (plus the first and last) against the oracle."""
+    from paper_1402_3501_amd import PATH_INT8
+    p = 251
+    rng = np.random.default_rng(29)
+    m, n, k = 4000, 4100, 300
+    assert ((m + 255) // 256) * ((n + 255) // 256) >= 256
+    rows = np.unique(np.concatenate([[0, m - 1], rng.choice(m, 40, replace=False)]))
+    for ta, tb in [(0, 0), (1, 0), (0, 1), (1, 1)]:
+        A = rng.integers(0, p, (k, m) if ta else (m, k)).astype(np.int32)
+        B = rng.integers(0, p, (n, k) if tb else (k, n)).astype(np.int32)
+        C = rng.integers(0, p, (m, n)).astype(np.int32)
+        alpha, beta = int(rng.integers(1, p)), int(rng.integers(1, p))
+        note("fgemm one limb wide", m, n, k, ta, tb)
+        Cd = dev(C)
+        lib.fgemm(dev(A), dev(B), Cd, p, alpha, beta, bool(ta), bool(tb), path=PATH_INT8)
+        got = host(Cd)
+        As = np.ascontiguousarray(A[:, rows] if ta else A[rows])
+        want = orc.fgemm(As, B, np.ascontiguousarray(C[rows]), p, alpha, beta, bool(ta), bool(tb))
+        assert np.array_equal(got[rows], want), (ta, tb)
+
+
+def test_pluq_int8_two_limbs(lib, orc):
+    """The factorisation with every product on two INT8 limbs (p = 32749),
+    uniform and rank-deficient, element by element against the oracle."""
+    from paper_1402_3501_amd import PATH_INT8
+    p = 32749
+    for A in [wl.uniform(600, 520, p, 41), wl.lowrank(700, 640, 300, p, 42)]:
+        note("pluq two limbs", A.shape)
+        want = orc.pluq(A, p)
+        Ad = dev(A)
+        res = lib.pluq(Ad, p, path=PATH_INT8)
+        assert res.rank == want.rank
+        assert np.array_equal(host(Ad), want.LU)
+        assert np.array_equal(res.P.cpu().numpy(), want.P) and np.array_equal(res.Q.cpu().numpy(), want.Q)
+
+
 def test_fgemm_submatrix_views(lib, orc):
     """Operands as strided views (leading dimension > columns, unaligned offsets)."""
     import torch
