@@ -73,7 +73,7 @@ def _summary(kernel: str, workload: str, what: str):
     import hashlib
     import re
     src = {"k_fgemm_f64": "fgemm_f64.hip", "k_fgemm_i8": "fgemm_i8.hip", "k_leaf_gen": "leaf64.hip",
-           "k_trsm": "ftrsm.hip", "k_split": "fgemm_i8.hip"}.get(kernel)
+           "k_trsm": "ftrsm.hip", "k_split": "fgemm_i8.hip", "k_pluq_batched": "batched.hip"}.get(kernel)
     prof = os.path.join(ROOT, "profiles", f"{kernel.replace('k_', '')}_{workload}_{what}.md")
     if src is None:
         return None
@@ -481,13 +481,53 @@ def bench_batched(args, spec):
     ranks_ok = bool(np.array_equal(holder["res"].rank.cpu().numpy()[:len(ms_h)], rs_h))
     mm, nn, rr = (x.astype(np.float64) for x in (ms_h, ns_h, rs_h))
     alg = float(np.sum(2 * mm * nn * rr - (mm + nn) * rr ** 2 + 2 * rr ** 3 / 3))
+    # the same steps again with the library's launch events on: the batched
+    # kernel's own time per launch
+    ffp.profile_reset()
+    ffp.profile_enable(True)
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ffp.profile_enable(False)
+    fams = ffp.profile_read_all()
+    roof = None
+    if "k_pluq_batched" in fams:
+        nl, kms = fams["k_pluq_batched"][0], fams["k_pluq_batched"][1]
+        # every multiply-add of the elimination is one FP64 fma (2 flops), as
+        # counted by 2mnr - (m+n)r^2 + 2r^3/3; the kernel is latency-bound,
+        # so its bound is the FP64 vector rate of the VALUs
+        ach = alg / (kms / nl * 1e-3)
+        roof = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP64, "traffic": None, "kernel": "k_pluq_batched",
+                "launches_per_step": nl / max(args.steps, 1), "avg_launch_us": kms * 1e3 / nl,
+                "ops_per_launch": alg, "algorithmic_bytes_per_launch": 8.0 * float(np.sum(mm * nn)),
+                "share_of_step": kms / max(args.steps, 1) / ms}
+        tr = _summary("k_pluq_batched", args.workload, "traffic")
+        if tr and "traffic_bytes_per_launch" in tr:
+            roof["traffic"] = tr["traffic_bytes_per_launch"]
     out = {"metric": "batched PLUQ mod p algorithmic Gop/s (sum of 2mnr - (m+n)r^2 + 2r^3/3)",
            "value": round(alg / (ms * 1e-3) / 1e9, 3), "unit": "Gop/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": args.workload, "matrices": int(len(ms_h)), "p": p, "seed": spec["seed"],
                       "tuned_shape": shape, "shape_ms": [round(x, 3) for x in shape_ms],
-                      "matrices_per_s": round(len(ms_h) / (ms * 1e-3), 1), "ranks_ok": ranks_ok}}
+                      "matrices_per_s": round(len(ms_h) / (ms * 1e-3), 1), "ranks_ok": ranks_ok},
+           "roofline": roof}
+    if not args.no_cpu:
+        from oracle import oracle as orc
+        threads = orc.num_threads()
+        ms_c, ns_c, rs_c, Ab_c, off_c = wl.batch(256, 16, 512, p, 5)
+        log(f"[bench] CPU oracle on a 256-matrix sample, {threads} threads ...")
+        t0 = time.perf_counter()
+        for i in range(len(ms_c)):
+            orc.pluq(Ab_c[off_c[i]:off_c[i] + ms_c[i] * ns_c[i]].reshape(ms_c[i], ns_c[i]), p, selfcheck=False)
+        tc = time.perf_counter() - t0
+        mc, nc, rc = (x.astype(np.float64) for x in (ms_c, ns_c, rs_c))
+        alg_c = float(np.sum(2 * mc * nc * rc - (mc + nc) * rc ** 2 + 2 * rc ** 3 / 3))
+        out["cpu_baseline"] = {"value": round(alg_c / tc / 1e9, 4), "unit": "Gop/s", "cores": threads, "kind": "oracle",
+                               "sample": f"256 matrices drawn like {args.workload} (seed 5), oracle PLUQ one after "
+                                         f"another, {tc:.2f} s on {threads} threads",
+                               "cpu_model": cpu_model(), "nproc": os.cpu_count()}
     print(json.dumps(out), flush=True)
 
 
