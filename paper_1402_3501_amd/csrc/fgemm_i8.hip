@@ -17,7 +17,10 @@
 // 16-byte MFMA operand is one contiguous load); the product kernel computes
 // a 128 x 128 block of C per workgroup, streaming 64-deep K tiles of all L
 // digit planes of both operands through LDS (double buffered) into 8 wave64s,
-// each owning a 32 x 64 sub-block.  Products with too few output blocks to
+// each owning a 32 x 64 sub-block; products too small to fill the chip with
+// such blocks take 64 x 64 blocks of 4 waves, and one-limb products large
+// enough take 256 x 256 blocks of 8 waves (64 x 128 each) with 128-deep K
+// tiles.  Products with too few output blocks to
 // fill the chip split K over several workgroups per block (each writes its
 // reduced partial result, a second kernel sums them mod p and applies alpha
 // and beta).
