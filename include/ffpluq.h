@@ -87,6 +87,9 @@ int ffp_auto_path(uint32_t p, int64_t m, int64_t n, int64_t k);
  * the inner dimension over up to 4 workgroups per block, with their partial
  * results (at most 4 m n int32, capped at 32 MiB) in the workspace and one
  * more launch to combine them.  The workspace query includes that room.
+ * A product with m + n beyond about 4.19e6 (65535 grid rows of 64 limb
+ * rows) runs on the FP64 path whatever the path argument (the same bits),
+ * or returns FFP_E_UNSUPPORTED when p is beyond that path.
  * -------------------------------------------------------------------------- */
 size_t ffp_fgemm_workspace(int transA, int transB, int64_t m, int64_t n, int64_t k, uint32_t p,
                            int path);

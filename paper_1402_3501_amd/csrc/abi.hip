@@ -35,7 +35,14 @@ int fgemm_any(int path, const Field &F, int ta, int tb, int64_t m, int64_t n, in
         if (path == FFP_PATH_INT8) ws.take(fgemm_i8_ws(F, m, n, k));
         return FFP_OK;
     }
-    const int eff = path == FFP_PATH_AUTO ? resolve_path(path, F.p, m, n, k) : path;
+    int eff = path == FFP_PATH_AUTO ? resolve_path(path, F.p, m, n, k) : path;
+    // the limb split runs one grid row per 64 plane rows (at most 65535): a
+    // taller product runs on the FP64 path (the same bits), or is refused
+    // when p is beyond that path
+    if (eff == FFP_PATH_INT8 && (m + n) / 64 + 8 > 65535) {
+        if (F.p > FFP_P_MAX_FP64) return FFP_E_UNSUPPORTED;
+        eff = FFP_PATH_FP64;
+    }
     if (eff == FFP_PATH_INT8 && F.limbs > 0 && k > 0)
         return fgemm_i8(F, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws, s);
     return fgemm_f64(F, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s);

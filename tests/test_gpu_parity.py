@@ -228,6 +228,24 @@ def test_pluq_int8_two_limbs(lib, orc):
         assert np.array_equal(res.P.cpu().numpy(), want.P) and np.array_equal(res.Q.cpu().numpy(), want.Q)
 
 
+def test_fgemm_int8_very_tall(lib, orc):
+    """An INT8 request for a product taller than the limb split's grid
+    (more than 65535 x 64 plane rows) runs on the FP64 path with the same
+    bits instead of failing."""
+    from paper_1402_3501_amd import PATH_INT8
+    p = 251
+    rng = np.random.default_rng(31)
+    m, n, k = 4300000, 2, 3
+    A = rng.integers(0, p, (m, k)).astype(np.int32)
+    B = rng.integers(0, p, (k, n)).astype(np.int32)
+    C = rng.integers(0, p, (m, n)).astype(np.int32)
+    note("fgemm very tall", m, n, k)
+    want = orc.fgemm(A, B, C, p, 7, 3)
+    Cd = dev(C)
+    lib.fgemm(dev(A), dev(B), Cd, p, 7, 3, path=PATH_INT8)
+    assert np.array_equal(host(Cd), want)
+
+
 def test_fgemm_submatrix_views(lib, orc):
     """Operands as strided views (leading dimension > columns, unaligned offsets)."""
     import torch
