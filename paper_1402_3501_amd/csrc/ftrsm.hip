@@ -194,21 +194,25 @@ constexpr int kTBB = 256;  // fused base case: up to four 64-blocks
 //   W_t = op(T)_tt^-1 (64 x 64 centred doubles), taken as is (left) or
 //   transposed (right).
 constexpr int kVB = 16;  // vectors per workgroup of the fused base case
+constexpr int kWideGroups = 1024;  // 16-wide groups from which the paired base runs 32 wide
 
 // NBT > 0: d == 64 NBT and T's rows are 16-byte aligned (host-checked), so
 // that the item count and every load's form are compile-time: no branch
 // between a fragment load and its use, and the loads of several items stay in
 // flight together (a branch join makes the wait conservative).
-template <bool LEFT, bool RED, int NBT = 0>
-__device__ __forceinline__ void trsm_blk_body(int bid, int d, int64_t nv, const int32_t *__restrict__ T,
-                                              int64_t ldt, int direct, int fwd, const double *__restrict__ W,
-                                              int32_t *__restrict__ B, int64_t ldb, double p, double pinv,
-                                              int32_t half, int ksteps) {
-    constexpr int KS = kTB / 4;           // k-steps per 64 x 16 x 64 product
-    __shared__ int32_t S[kTBB][kVB + 1];  // [component][vector]
+// VB vectors per workgroup (16 or 32): each wave then computes VB / 16
+// output tiles of 16 x 16 from the same operand fragments.
+template <bool LEFT, bool RED, int NBT = 0, int VB = kVB>
+__device__ __forceinline__ void trsm_blk_body(int32_t (&S)[kTBB][VB + 1], int bid, int d, int64_t nv,
+                                              const int32_t *__restrict__ T, int64_t ldt, int direct, int fwd,
+                                              const double *__restrict__ W, int32_t *__restrict__ B, int64_t ldb,
+                                              double p, double pinv, int32_t half, int ksteps) {
+    constexpr int KS = kTB / 4;  // k-steps per 64 x 16 x 64 product
+    constexpr int CT = VB / 16;  // column tiles per wave
+    // S: the slab in LDS, [component][vector]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, k4 = lane >> 4;
-    const int64_t v0 = (int64_t)bid * kVB;
+    const int64_t v0 = (int64_t)bid * VB;
     const int nb = NBT > 0 ? NBT : (d + kTB - 1) / kTB;
     const double hd = (double)half;
     const int32_t ip = (int32_t)p;
@@ -288,25 +292,35 @@ __device__ __forceinline__ void trsm_blk_body(int bid, int d, int64_t nv, const 
             }
         }
     };
-    v4d acc = {0.0, 0.0, 0.0, 0.0};
-    // ac += A S[row0 .. row0 + 63][*], A in registers
-    auto product = [&](const double (&av)[KS], int row0, v4d &ac) {
-        int32_t bv[KS];
+    v4d acc[CT];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) bv[ks] = S[row0 + 16 * k4 + ks][r16];
+    for (int ct = 0; ct < CT; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+    // ac += A S[row0 .. row0 + 63][*], A in registers, for each column tile
+    auto product = [&](const double (&av)[KS], int row0, v4d (&ac)[CT]) {
+        int32_t bv[CT][KS];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) bv[ct][ks] = S[row0 + 16 * k4 + ks][16 * ct + r16];
         int steps = 0;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            ac = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], (double)bv[ks], ac, 0, 0, 0);
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+                ac[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], (double)bv[ct][ks], ac[ct], 0, 0, 0);
             if (RED && ++steps == ksteps) {
                 steps = 0;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) ac[v] = mod_near(ac[v], p, pinv);
+                for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) ac[ct][v] = mod_near(ac[ct][v], p, pinv);
             }
         }
         // keep partial sums bounded across several products
 #pragma unroll
-        for (int v = 0; v < 4; ++v) ac[v] = mod_near(ac[v], p, pinv);
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ac[ct][v] = mod_near(ac[ct][v], p, pinv);
     };
 #pragma unroll
     for (int j = 0; j < PD; ++j)
@@ -314,12 +328,12 @@ __device__ __forceinline__ void trsm_blk_body(int bid, int d, int64_t nv, const 
     // (the slab's loads go out after the first operands': one wait covers both)
     // ---- slab in (clamped loads, zero outside)
     {
-        constexpr int PER = kTBB * kVB / 256;
+        constexpr int PER = kTBB * VB / 256;
         int32_t v[PER];
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * 256;
-            const int c = LEFT ? idx / kVB : idx % kTBB, w = LEFT ? idx % kVB : idx / kTBB;
+            const int c = LEFT ? idx / VB : idx % kTBB, w = LEFT ? idx % VB : idx / kTBB;
             const int cc = c < d ? c : d - 1;
             const int64_t vv = v0 + w < nv ? v0 + w : nv - 1;
             v[e] = LEFT ? B[(int64_t)cc * ldb + vv] : B[vv * ldb + cc];
@@ -327,7 +341,7 @@ __device__ __forceinline__ void trsm_blk_body(int bid, int d, int64_t nv, const 
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int idx = tid + e * 256;
-            const int c = LEFT ? idx / kVB : idx % kTBB, w = LEFT ? idx % kVB : idx / kTBB;
+            const int c = LEFT ? idx / VB : idx % kTBB, w = LEFT ? idx % VB : idx / kTBB;
             const int32_t x = (c < d && v0 + w < nv) ? v[e] : 0;
             S[c][w] = x > half ? x - ip : x;
         }
@@ -360,18 +374,25 @@ __device__ __forceinline__ void trsm_blk_body(int bid, int d, int64_t nv, const 
             if (q > 0) {
                 // S_t <- S_t - (sum of the source products)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = 64 * t + 16 * wave + k4 + 4 * v;
-                    S[row][r16] = (int32_t)cmod((double)S[row][r16] - acc[v], p, pinv, hd);
-                    acc[v] = 0.0;
-                }
+                for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 64 * t + 16 * wave + k4 + 4 * v;
+                        S[row][16 * ct + r16] = (int32_t)cmod((double)S[row][16 * ct + r16] - acc[ct][v], p, pinv, hd);
+                        acc[ct][v] = 0.0;
+                    }
                 __syncthreads();
             }
-            v4d x2 = {0.0, 0.0, 0.0, 0.0};
+            v4d x2[CT];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) x2[ct] = v4d{0.0, 0.0, 0.0, 0.0};
             product(av, 64 * t, x2);
             __syncthreads();  // every read of S_t is done
 #pragma unroll
-            for (int v = 0; v < 4; ++v) S[64 * t + 16 * wave + k4 + 4 * v][r16] = (int32_t)cmod(x2[v], p, pinv, hd);
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    S[64 * t + 16 * wave + k4 + 4 * v][16 * ct + r16] = (int32_t)cmod(x2[ct][v], p, pinv, hd);
             __syncthreads();
         }
     };
@@ -385,8 +406,8 @@ __device__ __forceinline__ void trsm_blk_body(int bid, int d, int64_t nv, const 
             if (it < nitems) run_item(it, ring[it % PD]);
     }
     // ---- slab out
-    for (int idx = tid; idx < kTBB * kVB; idx += 256) {
-        const int c = LEFT ? idx / kVB : idx % kTBB, w = LEFT ? idx % kVB : idx / kTBB;
+    for (int idx = tid; idx < kTBB * VB; idx += 256) {
+        const int c = LEFT ? idx / VB : idx % kTBB, w = LEFT ? idx % VB : idx / kTBB;
         if (c < d && v0 + w < nv) {
             const int32_t x = S[c][w];
             const int32_t y = x < 0 ? x + ip : x;
@@ -401,7 +422,8 @@ __global__ __launch_bounds__(256) void k_trsm_blk(int d, int64_t nv, const int32
                                                   int direct, int fwd, const double *__restrict__ W,
                                                   int32_t *__restrict__ B, int64_t ldb, double p, double pinv,
                                                   int32_t half, int ksteps) {
-    trsm_blk_body<LEFT, RED>(blockIdx.x, d, nv, T, ldt, direct, fwd, W, B, ldb, p, pinv, half, ksteps);
+    __shared__ int32_t S[kTBB][kVB + 1];
+    trsm_blk_body<LEFT, RED>(S, blockIdx.x, d, nv, T, ldt, direct, fwd, W, B, ldb, p, pinv, half, ksteps);
 }
 
 // The two panel solves of a generic block LU node in one launch, for a
@@ -417,15 +439,18 @@ __global__ __launch_bounds__(256) void k_trsm_apply_pair(int h, int gd, int64_t 
     if ((int)blockIdx.x < gd) trsm_apply_body<true, RED>(blockIdx.x, h, nvd, Li, Bd, ldb, p, pinv, half, ksteps);
     else trsm_apply_body<false, RED>(blockIdx.x - gd, h, nve, Ui, Be, ldb, p, pinv, half, ksteps);
 }
-template <bool RED, int NBT>
+template <bool RED, int NBT, int VB>
 __global__ __launch_bounds__(256) void k_trsm_blk_pair(int h, int gd, int64_t nvd, int32_t *__restrict__ Bd,
                                                        int64_t nve, int32_t *__restrict__ Be, int64_t ldb,
                                                        const int32_t *__restrict__ T, int64_t ldt,
                                                        const double *__restrict__ Li, const double *__restrict__ Ui,
                                                        double p, double pinv, int32_t half, int ksteps) {
+    __shared__ int32_t S[kTBB][VB + 1];  // one slab for either side
     if ((int)blockIdx.x < gd)
-        trsm_blk_body<true, RED, NBT>(blockIdx.x, h, nvd, T, ldt, 1, 1, Li, Bd, ldb, p, pinv, half, ksteps);
-    else trsm_blk_body<false, RED, NBT>(blockIdx.x - gd, h, nve, T, ldt, 0, 1, Ui, Be, ldb, p, pinv, half, ksteps);
+        trsm_blk_body<true, RED, NBT, VB>(S, blockIdx.x, h, nvd, T, ldt, 1, 1, Li, Bd, ldb, p, pinv, half, ksteps);
+    else
+        trsm_blk_body<false, RED, NBT, VB>(S, blockIdx.x - gd, h, nve, T, ldt, 0, 1, Ui, Be, ldb, p, pinv, half,
+                                           ksteps);
 }
 
 static int trsm_blk(const Field &F, int side, int d, int64_t nv, const int32_t *T, int64_t ldt, bool direct,
@@ -579,22 +604,31 @@ static int trsm_pair_base(const Field &F, int64_t h, const int32_t *T, int64_t l
 #undef FFP_AP
     } else {
         const bool red = F.kexact < kTB;
-        const int gd = (int)((nvd + kVB - 1) / kVB), ge = (int)((nve + kVB - 1) / kVB);
+        // 32 vectors per workgroup once the 16-wide grid holds at least
+        // kWideGroups groups: each operand fragment then feeds two MFMA tiles
+        const bool wide = (nvd + kVB - 1) / kVB + (nve + kVB - 1) / kVB >= kWideGroups;
+        const int vb = wide ? 2 * kVB : kVB;
+        const int gd = (int)((nvd + vb - 1) / vb), ge = (int)((nve + vb - 1) / vb);
         // whole 64-blocks and aligned rows: the item count is a template argument
         const bool aligned = (((uintptr_t)T | (uintptr_t)(ldt * 4)) & 15) == 0;
         const int nbt = (aligned && h % kTB == 0) ? (int)(h / kTB) : 0;
-#define FFP_BP(R_, N_)                                                                                          \
-    hipLaunchKernelGGL((k_trsm_blk_pair<R_, N_>), dim3((unsigned)(gd + ge)), dim3(256), 0, s, (int)h, gd, nvd, Bd, \
-                       nve, Be, ldb, T, ldt, Li, Ui, F.pd, F.pinv, (int32_t)F.half, ksteps)
-#define FFP_BPN(R_)                   \
-    switch (nbt) {                    \
-        case 2: FFP_BP(R_, 2); break; \
-        case 3: FFP_BP(R_, 3); break; \
-        case 4: FFP_BP(R_, 4); break; \
-        default: FFP_BP(R_, 0); break; \
+#define FFP_BP(R_, N_, V_)                                                                                   \
+    hipLaunchKernelGGL((k_trsm_blk_pair<R_, N_, V_>), dim3((unsigned)(gd + ge)), dim3(256), 0, s, (int)h, gd, \
+                       nvd, Bd, nve, Be, ldb, T, ldt, Li, Ui, F.pd, F.pinv, (int32_t)F.half, ksteps)
+#define FFP_BPN(R_, V_)                   \
+    switch (nbt) {                        \
+        case 2: FFP_BP(R_, 2, V_); break; \
+        case 3: FFP_BP(R_, 3, V_); break; \
+        case 4: FFP_BP(R_, 4, V_); break; \
+        default: FFP_BP(R_, 0, V_); break; \
     }
-        if (red) FFP_BPN(true)
-        else FFP_BPN(false)
+        if (wide) {
+            if (red) FFP_BPN(true, 2 * kVB)
+            else FFP_BPN(false, 2 * kVB)
+        } else {
+            if (red) FFP_BPN(true, kVB)
+            else FFP_BPN(false, kVB)
+        }
 #undef FFP_BPN
 #undef FFP_BP
     }

@@ -447,6 +447,18 @@ def test_pluq_general_path_on_generic_inputs(lib, orc):
         _pluq_compare(lib, orc, A, p, 0, "speculative")
 
 
+@pytest.mark.parametrize("p", [131071, 8388593, 94906249])
+def test_pluq_tall_and_wide_generic_panels(lib, orc, p):
+    """Generic blocks with one long side: a leading 128 x 128 tile whose two
+    panel solves together span more than 16384 vectors run the paired base
+    solve on 32-vector slabs, here with ragged slabs on both sides (72 and
+    16372 vectors); p = 94906249 reduces inside those solves."""
+    rng = np.random.default_rng(p % 1000 + 5)
+    for (m, n) in [(16500, 200), (200, 16500)]:
+        A = rng.integers(0, p, (m, n)).astype(np.int32)
+        _pluq_compare(lib, orc, A, p, 0, f"generic panels {m}x{n}")
+
+
 def test_pluq_generic_prefix_shortcuts(lib, orc):
     """Rank-deficient inputs whose leading minors are nonzero up to some order
     k0: the failed generic attempt's k0 lets leading tiles within that order
