@@ -16,11 +16,12 @@
 // zero-padded planes [digit][row][k] (k contiguous, so that each lane's
 // 16-byte MFMA operand is one contiguous load); the product kernel computes
 // a 128 x 128 block of C per workgroup, streaming 64-deep K tiles of all L
-// digit planes of both operands through LDS (double buffered) into 8 wave64s,
-// each owning a 32 x 64 sub-block; products too small to fill the chip with
-// such blocks take 64 x 64 blocks of 4 waves, and one-limb products large
-// enough take 256 x 256 blocks of 8 waves (64 x 128 each) with 128-deep K
-// tiles.  Products with too few output blocks to
+// digit planes of both operands into LDS with the direct global-to-LDS loads
+// (three buffers, each tile requested two tiles ahead) and from there into 8
+// wave64s, each owning a 32 x 64 sub-block; products too small to fill the
+// chip with such blocks take 64 x 64 blocks of 4 waves, and one-limb products
+// large enough take 256 x 256 blocks of 8 waves (64 x 128 each) with
+// 128-deep K tiles staged through registers (double-buffered LDS).  Products with too few output blocks to
 // fill the chip split K over several workgroups per block (each writes its
 // reduced partial result, a second kernel sums them mod p and applies alpha
 // and beta).
@@ -119,6 +120,47 @@ __global__ __launch_bounds__(256) void k_split(SplitSrc sa, SplitSrc sb, int64_t
 }
 
 // ------------------------------------------------------------------ product
+// epilogue: lane l holds rows 4*(l/16)+v, column l%16 of each 16x16 block
+// of the wave tile at (r0, c0); each shift class is reduced, recombined with
+// its weight 256^s mod p, then alpha, beta and the store (or the partial
+// result of K part z)
+template <int NS, int FM, int FN>
+__device__ __forceinline__ void i8_epilogue(const v4i (&acc)[NS][FM][FN], int64_t r0, int64_t c0, int lane, int64_t m,
+                                            int64_t n, int32_t *__restrict__ C, int64_t ldc, double p, double pinv,
+                                            double alpha, double beta, double w1, double w2, double w3, double w4,
+                                            int z, int32_t *__restrict__ part) {
+    const double w[5] = {1.0, w1, w2, w3, w4};
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int64_t gj = c0 + j * 16 + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t gi = r0 + i * 16 + (lane >> 4) * 4 + v;
+                if (gi < m && gj < n) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) t = fma(mod_near((double)acc[s][i][j][v], p, pinv), w[s], t);
+                    double rres = mod_canon(t, p, pinv);
+                    if (part) {
+                        part[((int64_t)z * m + gi) * n + gj] = (int32_t)rres;
+                        continue;
+                    }
+                    if (alpha != 1.0) rres = mod_canon(alpha * rres, p, pinv);
+                    if (beta != 0.0) {
+                        double c = (double)C[gi * ldc + gj];
+                        if (beta != 1.0) c = mod_canon(beta * c, p, pinv);
+                        rres += c;
+                        if (rres >= p) rres -= p;
+                    }
+                    C[gi * ldc + gj] = (int32_t)rres;
+                }
+            }
+        }
+    }
+}
+
 template <int L, int BM, int BN, int NT, int WM, int BK>
 __global__ __launch_bounds__(NT) void k_fgemm_i8(const int8_t *__restrict__ Ad, const int8_t *__restrict__ Bd,
                                                         int64_t Kp, int64_t planeA, int64_t planeB, int64_t m,
@@ -223,37 +265,149 @@ __global__ __launch_bounds__(NT) void k_fgemm_i8(const int8_t *__restrict__ Ad, 
         __syncthreads();
     }
 
-    // epilogue: lane l holds rows 4*(l/16)+v, column l%16 of each 16x16 block
-    const double w[5] = {1.0, w1, w2, w3, w4};
+    i8_epilogue<NS, FM, FN>(acc, m0 + wm0, n0 + wn0, lane, m, n, C, ldc, p, pinv, alpha, beta, w1, w2, w3, w4, z,
+                            part);
+}
+
+// One wave-wide direct load: lane l's 16 bytes at base + off (base
+// wave-uniform, off this lane's byte offset) go to LDS byte lds + 16 l.
+// Written as an instruction here (the builtin makes the compiler wait for
+// every such load before any later LDS read, which would serialise the
+// buffers): it has no result register, its LDS writes are covered by the
+// hand-counted waits of the caller, and the memory clobber keeps the
+// compiler's own LDS accesses on their side of it.
+__device__ __forceinline__ void lds_load16(const int8_t *base, uint32_t off, uint32_t lds) {
+    asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1"
+                 :
+                 : "v"(off), "s"(base), "s"(lds)
+                 : "memory", "m0");
+}
+// LDS byte address of a shared object
+template <typename T>
+__device__ __forceinline__ uint32_t lds_addr(T &x) {
+    return __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(__attribute__((address_space(3))) char *)&x);
+}
+
+// The same product with the K tiles brought into LDS by the direct loads of
+// gfx950 (global_load_lds_dwordx4: one wave instruction writes 64
+// consecutive 16-byte chunks, 1 KiB = 16 rows of 64 bytes), three buffers
+// deep: tile t + 2 is requested right after the barrier that opens tile t,
+// so every tile's loads have two tiles' products to arrive, and no registers
+// stage them.  Rows are unpadded; chunk q of tile row r sits at position
+// q ^ ((r / 4) % 4), so that each 16-lane group of a fragment read (16 rows,
+// one chunk) covers all 64 banks once.  The wait before each barrier counts
+// this wave's loads: at most one tile's (the next) may still be in flight.
+template <int L, int BM, int BN, int NT, int WM>
+__global__ __launch_bounds__(NT) void k_fgemm_i8_dma(const int8_t *__restrict__ Ad, const int8_t *__restrict__ Bd,
+                                                     int64_t Kp, int64_t planeA, int64_t planeB, int64_t m, int64_t n,
+                                                     int32_t *__restrict__ C, int64_t ldc, double p, double pinv,
+                                                     double alpha, double beta, double w1, double w2, double w3,
+                                                     double w4, int ntx, int nty, int64_t kt_per,
+                                                     int32_t *__restrict__ part) {
+    constexpr int BK = 64;
+    constexpr int NS = 2 * L - 1;
+    constexpr int NW = NT / 64;
+    constexpr int WGM = BM / WM, WGN = NW / WGM, WN = BN / WGN;
+    static_assert(WGM * WGN == NW && WN % 16 == 0, "wave grid covers the block");
+    constexpr int FM = WM / 16, FN = WN / 16;
+    // 16-row chunks of a tile per operand, and per wave
+    constexpr int CHA = L * BM / 16, CHB = L * BN / 16;
+    static_assert(CHA % NW == 0 && CHB % NW == 0, "every wave loads the same number of chunks");
+    constexpr int PWA = CHA / NW, PWB = CHB / NW, CHW = PWA + PWB;
+    static_assert(CHW <= 63, "wait count");
+    typedef int8_t TileA[L][BM][BK];
+    typedef int8_t TileB[L][BN][BK];
+    // one object per buffer: the compiler then sees that the loads into one
+    // buffer do not alias the fragment reads of another
+    __shared__ __attribute__((aligned(1024))) TileA A0, A1, A2;
+    __shared__ __attribute__((aligned(1024))) TileB B0, B1, B2;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
+    const int tiles = ntx * nty;
+    const int z = part ? (int)blockIdx.x / tiles : 0;
+    int ty, tx;
+    xcd_tile(part ? (int)blockIdx.x % tiles : (int)blockIdx.x, ntx, nty, ty, tx);
+    const int64_t m0 = (int64_t)ty * BM, n0 = (int64_t)tx * BN;
+    const int64_t t0 = part ? kt_per * z : 0;
+    const int64_t nt = part ? ((Kp / BK - t0) < kt_per ? Kp / BK - t0 : kt_per) : Kp / BK;
+
+    // lane -> (row lane / 4 of a 16-row chunk, position lane % 4): it loads
+    // the global 16 bytes that belong at that position; the same byte
+    // offset serves both operands (rows of Kp bytes)
+    const int crow = lane >> 2, cq = (lane & 3) ^ ((crow >> 2) & 3);
+    const uint32_t voff = (uint32_t)(crow * Kp + 16 * cq);
+    const uint32_t la[3] = {lds_addr(A0), lds_addr(A1), lds_addr(A2)};
+    const uint32_t lb[3] = {lds_addr(B0), lds_addr(B1), lds_addr(B2)};
+    // K tile t into buffer q (t clamped to the last tile: every step issues
+    // the same number of loads, so the wait counts hold; a clamped load only
+    // refills a buffer that is not read again)
+    auto issue = [&](int64_t t, int q) {
+        const int64_t k0 = (t0 + (t < nt ? t : nt - 1)) * BK;
 #pragma unroll
-    for (int i = 0; i < FM; ++i) {
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            const int64_t gj = n0 + wn0 + j * 16 + (lane & 15);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t gi = m0 + wm0 + i * 16 + (lane >> 4) * 4 + v;
-                if (gi < m && gj < n) {
-                    double t = 0.0;
-#pragma unroll
-                    for (int s = 0; s < NS; ++s) t = fma(mod_near((double)acc[s][i][j][v], p, pinv), w[s], t);
-                    double rres = mod_canon(t, p, pinv);
-                    if (part) {
-                        part[((int64_t)z * m + gi) * n + gj] = (int32_t)rres;
-                        continue;
-                    }
-                    if (alpha != 1.0) rres = mod_canon(alpha * rres, p, pinv);
-                    if (beta != 0.0) {
-                        double c = (double)C[gi * ldc + gj];
-                        if (beta != 1.0) c = mod_canon(beta * c, p, pinv);
-                        rres += c;
-                        if (rres >= p) rres -= p;
-                    }
-                    C[gi * ldc + gj] = (int32_t)rres;
-                }
-            }
+        for (int e = 0; e < PWA; ++e) {
+            const int c = wave + NW * e;  // wave-uniform
+            const int d = c / (BM / 16), rb = (c % (BM / 16)) * 16;
+            lds_load16(Ad + d * planeA + (m0 + rb) * Kp + k0, voff, la[q] + (uint32_t)((d * BM + rb) * BK));
         }
+#pragma unroll
+        for (int e = 0; e < PWB; ++e) {
+            const int c = wave + NW * e;
+            const int d = c / (BN / 16), rb = (c % (BN / 16)) * 16;
+            lds_load16(Bd + d * planeB + (n0 + rb) * Kp + k0, voff, lb[q] + (uint32_t)((d * BN + rb) * BK));
+        }
+    };
+
+    v4i acc[NS][FM][FN];
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[s][i][j] = v4i{0, 0, 0, 0};
+
+    // fragment reads: lane reads row r = lane % 16 of its 16-row block, the
+    // 16 bytes of reduction chunk lane / 16 (rows start at multiples of 16)
+    const int r = lane & 15, fpos = 16 * ((lane >> 4) ^ ((r >> 2) & 3));
+    // vmcnt(n), expcnt and lgkmcnt left alone
+    constexpr int kWaitNext = (CHW & 15) | ((CHW >> 4) << 14) | (0x7 << 4) | (0xF << 8);
+    // step on tile t in buffer (Ac, Bc); the loads of tile t + 2 go to buffer qn
+    auto step = [&](int64_t t, const TileA &Ac, const TileB &Bc, int qn) {
+        __builtin_amdgcn_s_waitcnt(kWaitNext);  // tile t is in (this wave's part)
+        __builtin_amdgcn_s_barrier();           // every wave's part; every read of buffer qn is done
+        asm volatile("" ::: "memory");
+        v4i a[L][FM];
+#pragma unroll
+        for (int d = 0; d < L; ++d)
+#pragma unroll
+            for (int i = 0; i < FM; ++i) a[d][i] = *(const v4i *)&Ac[d][wm0 + i * 16 + r][fpos];
+#pragma unroll
+        for (int db = 0; db < L; ++db) {
+            v4i b[FN];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) b[j] = *(const v4i *)&Bc[db][wn0 + j * 16 + r][fpos];
+            if (db == 0) issue(t + 2, qn);  // after the first fragment reads are on their way
+#pragma unroll
+            for (int da = 0; da < L; ++da)
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[da + db][i][j] =
+                            __builtin_amdgcn_mfma_i32_16x16x64_i8(a[da][i], b[j], acc[da + db][i][j], 0, 0, 0);
+        }
+    };
+    issue(0, 0);
+    issue(1, 1);
+    for (int64_t t = 0; t < nt; t += 3) {
+        step(t, A0, B0, 2);
+        if (t + 1 < nt) step(t + 1, A1, B1, 0);
+        if (t + 2 < nt) step(t + 2, A2, B2, 1);
     }
+    // no load may still write the LDS when the workgroup ends
+    __builtin_amdgcn_s_waitcnt((0x7 << 4) | (0xF << 8));
+    i8_epilogue<NS, FM, FN>(acc, m0 + wm0, n0 + wn0, lane, m, n, C, ldc, p, pinv, alpha, beta, w1, w2, w3, w4, z,
+                            part);
 }
 
 // C <- alpha * (sum of the nz partial results) + beta * C, all mod p (each
@@ -384,12 +538,12 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
             }
             if (wide) {
             } else if (small)
-                hipLaunchKernelGGL((k_fgemm_i8<L, kI8SmallB, kI8SmallB, kI8SmallThreads, 32, kI8BK>),
+                hipLaunchKernelGGL((k_fgemm_i8_dma<L, kI8SmallB, kI8SmallB, kI8SmallThreads, 32>),
                                    dim3((unsigned)(ntx * nty * nz)), dim3(kI8SmallThreads), 0, s, Ad, Bd, Kp, planeA,
                                    planeB, m, n, C, ldc, F.pd, F.pinv, (double)alpha, be, wts[0], wts[1], wts[2],
                                    wts[3], ntx, nty, kt_per, part);
             else
-                hipLaunchKernelGGL((k_fgemm_i8<L, kI8BM, kI8BN, kI8Threads, 32, kI8BK>), dim3((unsigned)(ntx * nty * nz)),
+                hipLaunchKernelGGL((k_fgemm_i8_dma<L, kI8BM, kI8BN, kI8Threads, 32>), dim3((unsigned)(ntx * nty * nz)),
                                    dim3(kI8Threads), 0, s, Ad, Bd, Kp, planeA, planeB, m, n, C, ldc, F.pd, F.pinv,
                                    (double)alpha, be, wts[0], wts[1], wts[2], wts[3], ntx, nty, kt_per, part);
         }
