@@ -20,8 +20,7 @@
 // (three buffers, each tile requested two tiles ahead) and from there into 8
 // wave64s, each owning a 32 x 64 sub-block; products too small to fill the
 // chip with such blocks take 64 x 64 blocks of 4 waves, and one-limb products
-// large enough take 256 x 256 blocks of 8 waves (64 x 128 each) with
-// 128-deep K tiles staged through registers (double-buffered LDS).  Products with too few output blocks to
+// large enough take 256 x 256 blocks of 8 waves (64 x 128 each).  Products with too few output blocks to
 // fill the chip split K over several workgroups per block (each writes its
 // reduced partial result, a second kernel sums them mod p and applies alpha
 // and beta).
@@ -38,9 +37,8 @@ constexpr int kI8Threads = 512;
 // 64 x 64 blocks of four waves (two workgroups per compute unit)
 constexpr int kI8SmallB = 64, kI8SmallThreads = 256;
 // one limb (one accumulator set) leaves the registers for 256 x 256 blocks of
-// eight waves with 64 x 128 wave tiles, 128 deep per barrier: eight times
-// the products per barrier, and twice the time to hide the next tile's loads
-constexpr int kI8WideB = 256, kI8WideBK = 128;
+// eight waves with 64 x 128 wave tiles: four times the products per barrier
+constexpr int kI8WideB = 256;
 // split-K: at most 4 parts, partial results at most 32 MiB
 constexpr int kI8MaxSplit = 4;
 constexpr int64_t kI8SplitBytes = (int64_t)32 << 20;
@@ -161,114 +159,6 @@ __device__ __forceinline__ void i8_epilogue(const v4i (&acc)[NS][FM][FN], int64_
     }
 }
 
-template <int L, int BM, int BN, int NT, int WM, int BK>
-__global__ __launch_bounds__(NT) void k_fgemm_i8(const int8_t *__restrict__ Ad, const int8_t *__restrict__ Bd,
-                                                        int64_t Kp, int64_t planeA, int64_t planeB, int64_t m,
-                                                        int64_t n, int32_t *__restrict__ C, int64_t ldc, double p,
-                                                        double pinv, double alpha, double beta, double w1,
-                                                        double w2, double w3, double w4, int ntx, int nty,
-                                                        int64_t kt_per, int32_t *__restrict__ part) {
-    constexpr int NS = 2 * L - 1;        // shift classes
-    constexpr int ROW = BK + 16;         // padded LDS row (bytes)
-    constexpr int QR = BK / 16;          // 16-byte chunks per row
-    // wave tiles of WM rows; the waves form WGM x WGN
-    constexpr int WGM = BM / WM, WGN = NT / 64 / WGM, WN = BN / WGN;
-    static_assert(WGM * WGN * 64 == NT && WN % 16 == 0, "wave grid covers the block");
-    constexpr int FM = WM / 16, FN = WN / 16;
-    __shared__ __attribute__((aligned(16))) int8_t As[2][L][BM][ROW];
-    __shared__ __attribute__((aligned(16))) int8_t Bs[2][L][BN][ROW];
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
-    // part != nullptr: workgroup b computes K tiles [kt_per z, kt_per (z + 1))
-    // of output block b % (ntx nty), z = b / (ntx nty), into part[z] (m x n)
-    const int tiles = ntx * nty;
-    const int z = part ? (int)blockIdx.x / tiles : 0;
-    int ty, tx;
-    xcd_tile(part ? (int)blockIdx.x % tiles : (int)blockIdx.x, ntx, nty, ty, tx);
-    const int64_t m0 = (int64_t)ty * BM, n0 = (int64_t)tx * BN;
-
-    // global -> register staging: L*(BM+BN)*BK/16 chunks of 16 bytes
-    constexpr int CH_A = L * BM * BK / 16, CH_B = L * BN * BK / 16;
-    constexpr int PER = (CH_A + CH_B + NT - 1) / NT;
-    v4i stage[PER];
-    auto load = [&](int64_t k0) {
-#pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int c = tid + e * NT;
-            if (c < CH_A) {
-                const int d = c / (BM * QR), rem = c % (BM * QR), row = rem / QR, q = rem % QR;
-                stage[e] = *(const v4i *)(Ad + d * planeA + (m0 + row) * Kp + k0 + q * 16);
-            } else if (c < CH_A + CH_B) {
-                const int cb = c - CH_A;
-                const int d = cb / (BN * QR), rem = cb % (BN * QR), row = rem / QR, q = rem % QR;
-                stage[e] = *(const v4i *)(Bd + d * planeB + (n0 + row) * Kp + k0 + q * 16);
-            }
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int c = tid + e * NT;
-            if (c < CH_A) {
-                const int d = c / (BM * QR), rem = c % (BM * QR), row = rem / QR, q = rem % QR;
-                *(v4i *)&As[buf][d][row][q * 16] = stage[e];
-            } else if (c < CH_A + CH_B) {
-                const int cb = c - CH_A;
-                const int d = cb / (BN * QR), rem = cb % (BN * QR), row = rem / QR, q = rem % QR;
-                *(v4i *)&Bs[buf][d][row][q * 16] = stage[e];
-            }
-        }
-    };
-
-    v4i acc[NS][FM][FN];
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j) acc[s][i][j] = v4i{0, 0, 0, 0};
-
-    const int64_t t0 = part ? kt_per * z : 0;
-    const int64_t nt = part ? ((Kp / BK - t0) < kt_per ? Kp / BK - t0 : kt_per) : Kp / BK;
-    load(t0 * BK);
-    store(0);
-    __syncthreads();
-    for (int64_t t = 0; t < nt; ++t) {
-        const int buf = (int)(t & 1);
-        if (t + 1 < nt) load((t0 + t + 1) * BK);
-        const int r = lane & 15;
-#pragma unroll
-        for (int h = 0; h < BK / 64; ++h) {
-        const int kq = (lane >> 4) * 16 + 64 * h;
-        v4i a[L][FM];
-#pragma unroll
-        for (int d = 0; d < L; ++d)
-#pragma unroll
-            for (int i = 0; i < FM; ++i) a[d][i] = *(const v4i *)&As[buf][d][wm0 + i * 16 + r][kq];
-#pragma unroll
-        for (int db = 0; db < L; ++db) {
-            v4i b[FN];
-#pragma unroll
-            for (int j = 0; j < FN; ++j) b[j] = *(const v4i *)&Bs[buf][db][wn0 + j * 16 + r][kq];
-#pragma unroll
-            for (int da = 0; da < L; ++da)
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j)
-                        acc[da + db][i][j] =
-                            __builtin_amdgcn_mfma_i32_16x16x64_i8(a[da][i], b[j], acc[da + db][i][j], 0, 0, 0);
-        }
-        }
-        if (t + 1 < nt) store(buf ^ 1);
-        __syncthreads();
-    }
-
-    i8_epilogue<NS, FM, FN>(acc, m0 + wm0, n0 + wn0, lane, m, n, C, ldc, p, pinv, alpha, beta, w1, w2, w3, w4, z,
-                            part);
-}
-
 // One wave-wide direct load: lane l's 16 bytes at base + off (base
 // wave-uniform, off this lane's byte offset) go to LDS byte lds + 16 l.
 // Written as an instruction here (the builtin makes the compiler wait for
@@ -288,17 +178,17 @@ __device__ __forceinline__ uint32_t lds_addr(T &x) {
     return __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(__attribute__((address_space(3))) char *)&x);
 }
 
-// The same product with the K tiles brought into LDS by the direct loads of
-// gfx950 (global_load_lds_dwordx4: one wave instruction writes 64
-// consecutive 16-byte chunks, 1 KiB = 16 rows of 64 bytes), three buffers
-// deep: tile t + 2 is requested right after the barrier that opens tile t,
+// The product: a BM x BN block of C per workgroup of NT threads, wave tiles
+// of WM rows.  The K tiles come into LDS by the direct loads of gfx950
+// (global_load_lds_dwordx4: one wave instruction writes 64 consecutive
+// 16-byte chunks, 1 KiB = 16 rows of 64 bytes), three buffers deep: tile t + 2 is requested right after the barrier that opens tile t,
 // so every tile's loads have two tiles' products to arrive, and no registers
 // stage them.  Rows are unpadded; chunk q of tile row r sits at position
 // q ^ ((r / 4) % 4), so that each 16-lane group of a fragment read (16 rows,
 // one chunk) covers all 64 banks once.  The wait before each barrier counts
 // this wave's loads: at most one tile's (the next) may still be in flight.
 template <int L, int BM, int BN, int NT, int WM>
-__global__ __launch_bounds__(NT) void k_fgemm_i8_dma(const int8_t *__restrict__ Ad, const int8_t *__restrict__ Bd,
+__global__ __launch_bounds__(NT) void k_fgemm_i8(const int8_t *__restrict__ Ad, const int8_t *__restrict__ Bd,
                                                      int64_t Kp, int64_t planeA, int64_t planeB, int64_t m, int64_t n,
                                                      int32_t *__restrict__ C, int64_t ldc, double p, double pinv,
                                                      double alpha, double beta, double w1, double w2, double w3,
@@ -437,8 +327,8 @@ static int64_t kchunk_for(int L) { return L == 1 ? 131072 : (L == 2 ? 65536 : 32
 
 // rows of the limb planes: zero-padded to whole blocks of the largest tile
 static int64_t plane_rows(int L, int64_t r) { return rup(r, L == 1 ? kI8WideB : kI8BM); }
-// and columns: zero-padded to whole K tiles of the deepest kernel
-static int64_t plane_k(int L) { return L == 1 ? kI8WideBK : kI8BK; }
+// and columns: zero-padded to whole K tiles
+static int64_t plane_k(int) { return kI8BK; }
 
 size_t fgemm_i8_ws(const Field &F, int64_t m, int64_t n, int64_t k) {
     const int L = F.limbs > 0 ? F.limbs : 3;
@@ -531,19 +421,19 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
                                4.0 * (part ? (double)nz : (be != 0.0 ? 2.0 : 1.0)) * (double)m * (double)n);
             if constexpr (L == 1) {
                 if (wide)
-                    hipLaunchKernelGGL((k_fgemm_i8<1, kI8WideB, kI8WideB, kI8Threads, 64, kI8WideBK>),
+                    hipLaunchKernelGGL((k_fgemm_i8<1, kI8WideB, kI8WideB, kI8Threads, 64>),
                                        dim3((unsigned)(ntx * nty * nz)), dim3(kI8Threads), 0, s, Ad, Bd, Kp, planeA,
                                        planeB, m, n, C, ldc, F.pd, F.pinv, (double)alpha, be, wts[0], wts[1], wts[2],
                                        wts[3], ntx, nty, kt_per, part);
             }
             if (wide) {
             } else if (small)
-                hipLaunchKernelGGL((k_fgemm_i8_dma<L, kI8SmallB, kI8SmallB, kI8SmallThreads, 32>),
+                hipLaunchKernelGGL((k_fgemm_i8<L, kI8SmallB, kI8SmallB, kI8SmallThreads, 32>),
                                    dim3((unsigned)(ntx * nty * nz)), dim3(kI8SmallThreads), 0, s, Ad, Bd, Kp, planeA,
                                    planeB, m, n, C, ldc, F.pd, F.pinv, (double)alpha, be, wts[0], wts[1], wts[2],
                                    wts[3], ntx, nty, kt_per, part);
             else
-                hipLaunchKernelGGL((k_fgemm_i8_dma<L, kI8BM, kI8BN, kI8Threads, 32>), dim3((unsigned)(ntx * nty * nz)),
+                hipLaunchKernelGGL((k_fgemm_i8<L, kI8BM, kI8BN, kI8Threads, 32>), dim3((unsigned)(ntx * nty * nz)),
                                    dim3(kI8Threads), 0, s, Ad, Bd, Kp, planeA, planeB, m, n, C, ldc, F.pd, F.pinv,
                                    (double)alpha, be, wts[0], wts[1], wts[2], wts[3], ntx, nty, kt_per, part);
         }

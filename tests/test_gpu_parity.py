@@ -191,7 +191,7 @@ def test_fgemm_int8_two_limbs(lib, orc, p):
 def test_fgemm_int8_one_limb_wide_blocks(lib, orc):
     """One-limb products large enough for the 256 x 256 blocks (at least 256
     of them), with ragged edges in both dimensions, K not a multiple of the
-    128-deep K tile, every transpose combination, alpha and beta; 40 sampled
+    64-deep K tile, every transpose combination, alpha and beta; 40 sampled
     rows (plus the first and last) against the oracle."""
     from paper_1402_3501_amd import PATH_INT8
     p = 251
