@@ -5,7 +5,7 @@ path: leaf eliminations, ftrsm, fgemm (Schur updates), flaswp rotations and
 the rank-profile extraction.  The default workload is the largest
 single-GPU configuration, n16384_p8388593 (16384 x 16384, entries uniform
 mod p = 8388593, whose centred residues take three signed 8-bit limbs), on
-the library's AUTO path (INT8-limb products from 0.8e9 field operations,
+the library's AUTO path (INT8-limb products from 0.5e9 field operations,
 FP64 below).  The pristine input stays resident in HBM; each step starts
 with a device-to-device copy of it (PLUQ works in place).
 value = (2 n^3 / 3) / step time, the paper's effective rate.

@@ -18,14 +18,14 @@ int resolve_path(int path, uint32_t p, int64_t m, int64_t n, int64_t k) {
     if (L == 0) return FFP_PATH_FP64;
     // one limb: one INT8 product replaces one FP64 product at 64x the peak;
     // several limbs: L^2 INT8 products, still several times the FP64 peak,
-    // once the product amortises the limb split (one more launch, ~20 us of
-    // fixed cost in all).  Measured on MI355X (p = 131071, whole-call time,
-    // INT8 with K split over workgroups where the block grid is small): 768^3
-    // 48 us FP64 / 45 us INT8, 1024 x 1024 x 512 49 / 42 us, 512^3 24 / 35
-    // us, 1024 x 1024 x 256 32 / 33 us: they cross near 0.8 * 10^9 field
-    // operations.
+    // once the product amortises the limb split (one more launch, ~16 us of
+    // fixed cost in all).  Measured on MI355X (p = 131071 and 8388593,
+    // whole-call time, FP64 / INT8): 256 x 4096 x 256 21 / 16 us, 1024 x 1024
+    // x 256 21 / 17 us, 512 x 1024 x 512 19 / 20 us, 768^3 36 / 20 us, 512^3
+    // 12 / 21 us, 256 x 2048 x 256 12 / 17 us: they cross near 0.5 * 10^9
+    // field operations.
     if (L == 1) return (k >= 128 && m * n >= 256 * 256) ? FFP_PATH_INT8 : FFP_PATH_FP64;
-    return 2.0 * (double)m * (double)n * (double)k >= 0.8e9 ? FFP_PATH_INT8 : FFP_PATH_FP64;
+    return 2.0 * (double)m * (double)n * (double)k >= 0.5e9 ? FFP_PATH_INT8 : FFP_PATH_FP64;
 }
 
 int fgemm_any(int path, const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,

@@ -120,11 +120,14 @@ def test_workspace_queries(lib):
 
 
 def test_auto_path_crossover(lib):
-    """AUTO takes INT8 products from 0.8e9 field operations (several limbs) and,
+    """AUTO takes INT8 products from 0.5e9 field operations (several limbs) and,
     with one limb, from k >= 128 and 256 x 256 outputs."""
     assert lib.ffp_auto_path(131071, 768, 768, 768) == 2       # 0.91e9
     assert lib.ffp_auto_path(131071, 512, 512, 512) == 1       # 0.27e9
-    assert lib.ffp_auto_path(131071, 1024, 1024, 256) == 1     # 0.54e9
+    assert lib.ffp_auto_path(131071, 1024, 1024, 256) == 2     # 0.54e9
+    assert lib.ffp_auto_path(8388593, 256, 2048, 256) == 1     # 0.27e9
+    assert lib.ffp_auto_path(8388593, 992, 1008, 250) == 1     # 0.49999e9
+    assert lib.ffp_auto_path(8388593, 1000, 1000, 250) == 2    # exactly 0.5e9
     assert lib.ffp_auto_path(251, 256, 256, 128) == 2
     assert lib.ffp_auto_path(251, 256, 256, 127) == 1
     assert lib.ffp_auto_path(94906249, 8192, 8192, 8192) == 1  # beyond the INT8 limbs
