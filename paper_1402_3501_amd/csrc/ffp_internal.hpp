@@ -105,6 +105,11 @@ size_t fgemm_i8_split_ws(int64_t m, int64_t n);
 int fgemm_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
              const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta,
              int32_t *C, int64_t ldc, Arena &ws, hipStream_t s);
+// two independent products of the same k (no transposes) in one split and one product launch
+int fgemm_i8_pair(const Field &F, int64_t k, uint32_t alpha, uint32_t beta, int64_t m0, int64_t n0,
+                  const int32_t *A0, int64_t lda0, const int32_t *B0, int64_t ldb0, int32_t *C0, int64_t ldc0,
+                  int64_t m1, int64_t n1, const int32_t *A1, int64_t lda1, const int32_t *B1, int64_t ldb1, int32_t *C1,
+                  int64_t ldc1, Arena &ws, hipStream_t s);
 
 // dispatch on path (FFP_PATH_FP64 / FFP_PATH_INT8, AUTO already resolved)
 int fgemm_any(int path, const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k,

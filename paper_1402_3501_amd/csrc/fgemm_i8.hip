@@ -57,19 +57,23 @@ struct SplitSrc {
     int8_t *dst;
 };
 
-// Both operands of a product in one launch: row tiles [0, rtA) are A's, the
-// rest B's.
+// The operands of one product, or of two with the same K, in one launch:
+// operand i takes the row tiles [end[i - 1], end[i]) of the grid (end[-1] = 0).
+struct SplitSet {
+    SplitSrc src[4];
+    int64_t end[4];
+};
 template <int L>
-__global__ __launch_bounds__(256) void k_split(SplitSrc sa, SplitSrc sb, int64_t rtA, int64_t K, int64_t Kp,
-                                               int32_t half, int32_t p) {
-    const bool isb = (int64_t)blockIdx.y >= rtA;
-    const int32_t *__restrict__ X = isb ? sb.X : sa.X;
-    const int64_t sr = isb ? sb.sr : sa.sr, sk = isb ? sb.sk : sa.sk, R = isb ? sb.R : sa.R;
-    const int64_t plane = isb ? sb.plane : sa.plane;
-    int8_t *__restrict__ dst = isb ? sb.dst : sa.dst;
+__global__ __launch_bounds__(256) void k_split(SplitSet set, int64_t K, int64_t Kp, int32_t half, int32_t p) {
+    const int64_t by = blockIdx.y;
+    const int i = by < set.end[0] ? 0 : (by < set.end[1] ? 1 : (by < set.end[2] ? 2 : 3));
+    const SplitSrc &sc = set.src[i];
+    const int32_t *__restrict__ X = sc.X;
+    const int64_t sr = sc.sr, sk = sc.sk, R = sc.R, plane = sc.plane;
+    int8_t *__restrict__ dst = sc.dst;
     __shared__ int32_t tile[64][65];
     const int tid = threadIdx.x;
-    const int64_t r0 = ((int64_t)blockIdx.y - (isb ? rtA : 0)) * 64, k0 = (int64_t)blockIdx.x * 64;
+    const int64_t r0 = (by - (i > 0 ? set.end[i - 1] : 0)) * 64, k0 = (int64_t)blockIdx.x * 64;
     const bool along_k = sk == 1;
     // unconditional loads (addresses clamped into the operand) so that all 16
     // are in flight together; out-of-range elements are zeroed afterwards
@@ -165,7 +169,9 @@ __device__ __forceinline__ void i8_epilogue(const v4i (&acc)[NS][FM][FN], int64_
 // every such load before any later LDS read, which would serialise the
 // buffers): it has no result register, its LDS writes are covered by the
 // hand-counted waits of the caller, and the memory clobber keeps the
-// compiler's own LDS accesses on their side of it.
+// compiler's own LDS accesses on their side of it.  The compiler reserves
+// m0 (it warns about the clobber): none of the code it emits for these
+// kernels reads m0, so the value written here is never one it relies on.
 __device__ __forceinline__ void lds_load16(const int8_t *base, uint32_t off, uint32_t lds) {
     asm volatile("s_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %0, %1"
                  :
@@ -187,13 +193,19 @@ __device__ __forceinline__ uint32_t lds_addr(T &x) {
 // q ^ ((r / 4) % 4), so that each 16-lane group of a fragment read (16 rows,
 // one chunk) covers all 64 banks once.  The wait before each barrier counts
 // this wave's loads: at most one tile's (the next) may still be in flight.
+// One grid may run two products of the same K (the two panel products of a
+// generic node's solves): workgroups [0, g0) take P0, the rest P1.
+struct I8Prod {
+    const int8_t *A, *B;  // limb planes
+    int64_t planeA, planeB, m, n;
+    int32_t *C;
+    int64_t ldc;
+    int ntx, nty;  // output blocks
+};
 template <int L, int BM, int BN, int NT, int WM>
-__global__ __launch_bounds__(NT) void k_fgemm_i8(const int8_t *__restrict__ Ad, const int8_t *__restrict__ Bd,
-                                                     int64_t Kp, int64_t planeA, int64_t planeB, int64_t m, int64_t n,
-                                                     int32_t *__restrict__ C, int64_t ldc, double p, double pinv,
-                                                     double alpha, double beta, double w1, double w2, double w3,
-                                                     double w4, int ntx, int nty, int64_t kt_per,
-                                                     int32_t *__restrict__ part) {
+__global__ __launch_bounds__(NT) void k_fgemm_i8(I8Prod P0, I8Prod P1, int g0, int64_t Kp, double p, double pinv,
+                                                 double alpha, double beta, double w1, double w2, double w3, double w4,
+                                                 int64_t kt_per, int32_t *__restrict__ part) {
     constexpr int BK = 64;
     constexpr int NS = 2 * L - 1;
     constexpr int NW = NT / 64;
@@ -214,10 +226,20 @@ __global__ __launch_bounds__(NT) void k_fgemm_i8(const int8_t *__restrict__ Ad, 
 
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
+    const bool second = (int)blockIdx.x >= g0;
+    const int bid = second ? (int)blockIdx.x - g0 : (int)blockIdx.x;
+    const int8_t *__restrict__ Ad = second ? P1.A : P0.A;
+    const int8_t *__restrict__ Bd = second ? P1.B : P0.B;
+    const int64_t planeA = second ? P1.planeA : P0.planeA, planeB = second ? P1.planeB : P0.planeB;
+    const int64_t m = second ? P1.m : P0.m, n = second ? P1.n : P0.n, ldc = second ? P1.ldc : P0.ldc;
+    int32_t *__restrict__ C = second ? P1.C : P0.C;
+    const int ntx = second ? P1.ntx : P0.ntx, nty = second ? P1.nty : P0.nty;
+    // part != nullptr (one product only): workgroup b computes K tiles
+    // [kt_per z, kt_per (z + 1)) of output block b % (ntx nty), z = b / (ntx nty), into part[z] (m x n)
     const int tiles = ntx * nty;
-    const int z = part ? (int)blockIdx.x / tiles : 0;
+    const int z = part ? bid / tiles : 0;
     int ty, tx;
-    xcd_tile(part ? (int)blockIdx.x % tiles : (int)blockIdx.x, ntx, nty, ty, tx);
+    xcd_tile(part ? bid % tiles : bid, ntx, nty, ty, tx);
     const int64_t m0 = (int64_t)ty * BM, n0 = (int64_t)tx * BN;
     const int64_t t0 = part ? kt_per * z : 0;
     const int64_t nt = part ? ((Kp / BK - t0) < kt_per ? Kp / BK - t0 : kt_per) : Kp / BK;
@@ -357,12 +379,29 @@ static int i8_split(int64_t tiles, int64_t nt, int64_t m, int64_t n) {
     return z;
 }
 
+// One product C = alpha op(A) op(B) + beta C of a run (op as ta / tb).
+struct I8Call {
+    int64_t m, n;
+    const int32_t *A;
+    int64_t lda;
+    const int32_t *B;
+    int64_t ldb;
+    int32_t *C;
+    int64_t ldc;
+};
+
+// nc = 1 or 2 products of the same k, alpha, beta and transposes: their limb
+// splits share one launch and their products one grid (two products never
+// split K).
 template <int L>
-static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
-                  const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta, int32_t *C,
-                  int64_t ldc, Arena &ws, hipStream_t s) {
+static int run_i8(const Field &F, int ta, int tb, int64_t k, uint32_t alpha, uint32_t beta, const I8Call *cs,
+                  int nc, Arena &ws, hipStream_t s) {
     const int64_t KC = kchunk_for(L);
-    const int64_t Mp = plane_rows(L, m), Np = plane_rows(L, n);
+    int64_t Mp[2], Np[2];
+    for (int i = 0; i < nc; ++i) {
+        Mp[i] = plane_rows(L, cs[i].m);
+        Np[i] = plane_rows(L, cs[i].n);
+    }
     double wts[4] = {0, 0, 0, 0};
     {
         uint64_t x = 1;
@@ -371,76 +410,102 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
             wts[i] = (double)x;
         }
     }
+    // output blocks: 128 x 128 when they fill the chip's 256 compute units,
+    // else 64 x 64 (measured on MI355X: 1024^3 with three limbs 31 us against
+    // 36 us, the 16384 factorisation 34.3 against 35.0 ms); one limb takes
+    // 256 x 256 blocks whenever they fill the chip
+    int64_t t256 = 0, t128 = 0;
+    for (int i = 0; i < nc; ++i) {
+        t256 += (rup(cs[i].n, kI8WideB) / kI8WideB) * (rup(cs[i].m, kI8WideB) / kI8WideB);
+        t128 += (rup(cs[i].n, kI8BN) / kI8BN) * (rup(cs[i].m, kI8BM) / kI8BM);
+    }
+    const bool wide = L == 1 && t256 >= 256;
+    const bool small = !wide && t128 < 256;
+    const int bs = wide ? kI8WideB : (small ? kI8SmallB : kI8BM);
     for (int64_t kc0 = 0; kc0 < k; kc0 += KC) {
         const int64_t kc = k - kc0 < KC ? k - kc0 : KC;
         const int64_t Kp = rup(kc, plane_k(L));
         const size_t mk = ws.mark();
-        const int64_t planeA = Mp * Kp, planeB = Np * Kp;
-        int8_t *Ad = (int8_t *)ws.take((size_t)L * planeA);
-        int8_t *Bd = (int8_t *)ws.take((size_t)L * planeB);
-        if (!Ad || !Bd) return FFP_E_WORKSPACE;
-        // op(A)[i][kk] and op(B)[kk][j] as (row, k) accessors
-        const int32_t *Ab = ta ? A + kc0 * lda : A + kc0;
-        const int32_t *Bb = tb ? B + kc0 : B + kc0 * ldb;
-        const int64_t asr = ta ? 1 : lda, ask = ta ? lda : 1;
-        const int64_t bsr = tb ? ldb : 1, bsk = tb ? 1 : ldb;
-        const SplitSrc sa{Ab, asr, ask, m, planeA, Ad}, sb{Bb, bsr, bsk, n, planeB, Bd};
+        SplitSet set;
+        I8Prod P[2];
+        int64_t rows = 0;
+        double split_bytes = 0.0, ops = 0.0, prod_bytes = 0.0;
+        for (int i = 0; i < nc; ++i) {
+            const I8Call &c = cs[i];
+            const int64_t planeA = Mp[i] * Kp, planeB = Np[i] * Kp;
+            int8_t *Ad = (int8_t *)ws.take((size_t)L * planeA);
+            int8_t *Bd = (int8_t *)ws.take((size_t)L * planeB);
+            if (!Ad || !Bd) return FFP_E_WORKSPACE;
+            // op(A)[i][kk] and op(B)[kk][j] as (row, k) accessors
+            const int32_t *Ab = ta ? c.A + kc0 * c.lda : c.A + kc0;
+            const int32_t *Bb = tb ? c.B + kc0 : c.B + kc0 * c.ldb;
+            const int64_t asr = ta ? 1 : c.lda, ask = ta ? c.lda : 1;
+            const int64_t bsr = tb ? c.ldb : 1, bsk = tb ? 1 : c.ldb;
+            set.src[2 * i] = SplitSrc{Ab, asr, ask, c.m, planeA, Ad};
+            set.src[2 * i + 1] = SplitSrc{Bb, bsr, bsk, c.n, planeB, Bd};
+            set.end[2 * i] = (rows += Mp[i] / 64);
+            set.end[2 * i + 1] = (rows += Np[i] / 64);
+            split_bytes += 4.0 * (double)kc * (double)(c.m + c.n) + (double)L * (double)Kp * (double)(Mp[i] + Np[i]);
+            P[i] = I8Prod{Ad, Bd, planeA, planeB, c.m, c.n, c.C, c.ldc, (int)(rup(c.n, bs) / bs),
+                          (int)(rup(c.m, bs) / bs)};
+        }
+        for (int j = 2 * nc; j < 4; ++j) {
+            set.src[j] = set.src[2 * nc - 1];
+            set.end[j] = rows;
+        }
         {
-            ProfScope prof(PK_I8_SPLIT, 0.0, s, 4.0 * (double)kc * (double)(m + n) + (double)L * (double)Kp * (double)(Mp + Np));
-            hipLaunchKernelGGL((k_split<L>), dim3((unsigned)(Kp / 64), (unsigned)((Mp + Np) / 64)), dim3(256), 0, s,
-                               sa, sb, Mp / 64, kc, Kp, (int32_t)F.half, (int32_t)F.p);
+            ProfScope prof(PK_I8_SPLIT, 0.0, s, split_bytes);
+            hipLaunchKernelGGL((k_split<L>), dim3((unsigned)(Kp / 64), (unsigned)rows), dim3(256), 0, s, set, kc, Kp,
+                               (int32_t)F.half, (int32_t)F.p);
         }
         const double be = kc0 == 0 ? (double)beta : 1.0;
-        // 128 x 128 blocks when they fill the chip's 256 compute units, else
-        // 64 x 64 blocks (measured on MI355X: 1024^3 with three limbs 31 us
-        // against 36 us, the 16384 factorisation 34.3 against 35.0 ms); one
-        // limb takes 256 x 256 blocks whenever they fill the chip
-        const bool wide = L == 1 && (rup(n, kI8WideB) / kI8WideB) * (rup(m, kI8WideB) / kI8WideB) >= 256;
-        const bool small = !wide && (rup(n, kI8BN) / kI8BN) * (rup(m, kI8BM) / kI8BM) < 256;
-        const int bs = wide ? kI8WideB : (small ? kI8SmallB : kI8BM);
-        const int ntx = (int)(rup(n, bs) / bs), nty = (int)(rup(m, bs) / bs);
         const int64_t nt = Kp / kI8BK;
-        int nz = i8_split((int64_t)ntx * nty, nt, m, n);
+        const int64_t m0 = cs[0].m, n0 = cs[0].n;
+        int nz = nc == 1 ? i8_split((int64_t)P[0].ntx * P[0].nty, nt, m0, n0) : 1;
         int64_t kt_per = (nt + nz - 1) / nz;
         nz = (int)((nt + kt_per - 1) / kt_per);  // every part non-empty
         // optional: without room for the partial results the product runs unsplit
         int32_t *part = nullptr;
         if (nz > 1) {
-            const size_t bytes = (size_t)nz * (size_t)m * (size_t)n * 4;
+            const size_t bytes = (size_t)nz * (size_t)m0 * (size_t)n0 * 4;
             if (ws.used + bytes + 256 <= ws.cap) part = (int32_t *)ws.take(bytes);
         }
         if (!part) {
             nz = 1;
             kt_per = nt;
         }
+        // algorithmic bytes: the limb planes read once, the result written
+        // once (and C read once when beta != 0)
+        for (int i = 0; i < nc; ++i) {
+            const double m = (double)cs[i].m, n = (double)cs[i].n;
+            ops += 2.0 * m * n * (double)kc;
+            prod_bytes += (double)L * (m + n) * (double)kc + 4.0 * (part ? (double)nz : (be != 0.0 ? 2.0 : 1.0)) * m * n;
+        }
+        const int g0 = P[0].ntx * P[0].nty * nz;
+        const int grid = g0 + (nc == 2 ? P[1].ntx * P[1].nty : 0);
+        const I8Prod &P1 = P[nc - 1];
         {
-            // algorithmic bytes: the limb planes read once, the result written
-            // once (and C read once when beta != 0)
-            ProfScope prof(PK_FGEMM_I8, 2.0 * (double)m * (double)n * (double)kc, s,
-                           (double)L * ((double)m * (double)kc + (double)kc * (double)n) +
-                               4.0 * (part ? (double)nz : (be != 0.0 ? 2.0 : 1.0)) * (double)m * (double)n);
+            ProfScope prof(PK_FGEMM_I8, ops, s, prod_bytes);
             if constexpr (L == 1) {
                 if (wide)
-                    hipLaunchKernelGGL((k_fgemm_i8<1, kI8WideB, kI8WideB, kI8Threads, 64>),
-                                       dim3((unsigned)(ntx * nty * nz)), dim3(kI8Threads), 0, s, Ad, Bd, Kp, planeA,
-                                       planeB, m, n, C, ldc, F.pd, F.pinv, (double)alpha, be, wts[0], wts[1], wts[2],
-                                       wts[3], ntx, nty, kt_per, part);
+                    hipLaunchKernelGGL((k_fgemm_i8<1, kI8WideB, kI8WideB, kI8Threads, 64>), dim3((unsigned)grid),
+                                       dim3(kI8Threads), 0, s, P[0], P1, g0, Kp, F.pd, F.pinv, (double)alpha, be,
+                                       wts[0], wts[1], wts[2], wts[3], kt_per, part);
             }
             if (wide) {
             } else if (small)
-                hipLaunchKernelGGL((k_fgemm_i8<L, kI8SmallB, kI8SmallB, kI8SmallThreads, 32>),
-                                   dim3((unsigned)(ntx * nty * nz)), dim3(kI8SmallThreads), 0, s, Ad, Bd, Kp, planeA,
-                                   planeB, m, n, C, ldc, F.pd, F.pinv, (double)alpha, be, wts[0], wts[1], wts[2],
-                                   wts[3], ntx, nty, kt_per, part);
+                hipLaunchKernelGGL((k_fgemm_i8<L, kI8SmallB, kI8SmallB, kI8SmallThreads, 32>), dim3((unsigned)grid),
+                                   dim3(kI8SmallThreads), 0, s, P[0], P1, g0, Kp, F.pd, F.pinv, (double)alpha, be,
+                                   wts[0], wts[1], wts[2], wts[3], kt_per, part);
             else
-                hipLaunchKernelGGL((k_fgemm_i8<L, kI8BM, kI8BN, kI8Threads, 32>), dim3((unsigned)(ntx * nty * nz)),
-                                   dim3(kI8Threads), 0, s, Ad, Bd, Kp, planeA, planeB, m, n, C, ldc, F.pd, F.pinv,
-                                   (double)alpha, be, wts[0], wts[1], wts[2], wts[3], ntx, nty, kt_per, part);
+                hipLaunchKernelGGL((k_fgemm_i8<L, kI8BM, kI8BN, kI8Threads, 32>), dim3((unsigned)grid),
+                                   dim3(kI8Threads), 0, s, P[0], P1, g0, Kp, F.pd, F.pinv, (double)alpha, be, wts[0],
+                                   wts[1], wts[2], wts[3], kt_per, part);
         }
         if (part) {
-            ProfScope prof(PK_I8_COMBINE, 0.0, s, 4.0 * ((double)nz + (be != 0.0 ? 2.0 : 1.0)) * (double)m * (double)n);
-            hipLaunchKernelGGL(k_i8_combine, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0, s, m, n,
-                               nz, part, C, ldc, F.pd, F.pinv, (double)alpha, be);
+            ProfScope prof(PK_I8_COMBINE, 0.0, s, 4.0 * ((double)nz + (be != 0.0 ? 2.0 : 1.0)) * (double)m0 * (double)n0);
+            hipLaunchKernelGGL(k_i8_combine, dim3((unsigned)((n0 + 255) / 256), (unsigned)m0), dim3(256), 0, s, m0,
+                               n0, nz, part, cs[0].C, cs[0].ldc, F.pd, F.pinv, (double)alpha, be);
         }
         FFP_HIP_CHECK(hipGetLastError());
         ws.release(mk);
@@ -448,17 +513,46 @@ static int run_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t 
     return FFP_OK;
 }
 
+static int run_i8_any(const Field &F, int ta, int tb, int64_t k, uint32_t alpha, uint32_t beta, const I8Call *cs,
+                      int nc, Arena &ws, hipStream_t s) {
+    switch (F.limbs) {
+        case 1: return run_i8<1>(F, ta, tb, k, alpha, beta, cs, nc, ws, s);
+        case 2: return run_i8<2>(F, ta, tb, k, alpha, beta, cs, nc, ws, s);
+        case 3: return run_i8<3>(F, ta, tb, k, alpha, beta, cs, nc, ws, s);
+        default: return FFP_E_P_RANGE;
+    }
+}
+
 int fgemm_i8(const Field &F, int ta, int tb, int64_t m, int64_t n, int64_t k, uint32_t alpha,
              const int32_t *A, int64_t lda, const int32_t *B, int64_t ldb, uint32_t beta, int32_t *C,
              int64_t ldc, Arena &ws, hipStream_t s) {
     if (m <= 0 || n <= 0) return FFP_OK;
     if (k <= 0) return fgemm_f64(F, ta, tb, m, n, 0, alpha, A, lda, B, ldb, beta, C, ldc, s);
-    switch (F.limbs) {
-        case 1: return run_i8<1>(F, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws, s);
-        case 2: return run_i8<2>(F, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws, s);
-        case 3: return run_i8<3>(F, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, ws, s);
-        default: return FFP_E_P_RANGE;
+    const I8Call c{m, n, A, lda, B, ldb, C, ldc};
+    return run_i8_any(F, ta, tb, k, alpha, beta, &c, 1, ws, s);
+}
+
+// Two independent products C_i = alpha A_i B_i + beta C_i of the same k
+// (no transposes) in one limb-split launch and one product grid, when both
+// are small enough for the split's grid and k for one chunk; otherwise one
+// after the other.
+int fgemm_i8_pair(const Field &F, int64_t k, uint32_t alpha, uint32_t beta, int64_t m0, int64_t n0,
+                  const int32_t *A0, int64_t lda0, const int32_t *B0, int64_t ldb0, int32_t *C0, int64_t ldc0,
+                  int64_t m1, int64_t n1, const int32_t *A1, int64_t lda1, const int32_t *B1, int64_t ldb1, int32_t *C1,
+                  int64_t ldc1, Arena &ws, hipStream_t s) {
+    const int L = F.limbs;
+    if (ws.counting) {
+        ws.take(fgemm_i8_ws(F, m0, n0, k));
+        ws.take(fgemm_i8_ws(F, m1, n1, k));
+        return FFP_OK;
     }
+    const int64_t rows = (plane_rows(L, m0) + plane_rows(L, n0) + plane_rows(L, m1) + plane_rows(L, n1)) / 64;
+    if (m0 <= 0 || n0 <= 0 || m1 <= 0 || n1 <= 0 || k <= 0 || k > kchunk_for(L) || rows > 65535) {
+        FFP_CHECK(fgemm_any(FFP_PATH_INT8, F, 0, 0, m0, n0, k, alpha, A0, lda0, B0, ldb0, beta, C0, ldc0, ws, s));
+        return fgemm_any(FFP_PATH_INT8, F, 0, 0, m1, n1, k, alpha, A1, lda1, B1, ldb1, beta, C1, ldc1, ws, s);
+    }
+    const I8Call cs[2] = {{m0, n0, A0, lda0, B0, ldb0, C0, ldc0}, {m1, n1, A1, lda1, B1, ldb1, C1, ldc1}};
+    return run_i8_any(F, 0, 0, k, alpha, beta, cs, 2, ws, s);
 }
 
 }  // namespace ffp

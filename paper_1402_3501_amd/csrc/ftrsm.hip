@@ -657,6 +657,10 @@ int ftrsm_pair_gen(int path, const Field &F, int64_t h, const int32_t *T, int64_
     if (!ws.counting && nvd > 0 && nve > 0 && on_fp64(d2, nvd) && on_fp64(nve, d2)) {
         FFP_CHECK(fgemm_f64_pair(F, d2, nvd, T + d1 * ldt, ldt, Bd, ldb, Bd + d1 * ldb, ldb, nve, d2, Be, ldb, T + d1,
                                  ldt, Be + d1, ldb, d1, minus1, 1, s));
+    } else if (nvd > 0 && nve > 0 && F.limbs > 0 && !on_fp64(d2, nvd) && !on_fp64(nve, d2)) {
+        // both on INT8: one limb split and one product grid for the two
+        FFP_CHECK(fgemm_i8_pair(F, d1, minus1, 1, d2, nvd, T + d1 * ldt, ldt, Bd, ldb, Bd + d1 * ldb, ldb, nve, d2,
+                                Be, ldb, T + d1, ldt, Be + d1, ldb, ws, s));
     } else {
         if (nvd > 0)
             FFP_CHECK(fgemm_any(path, F, 0, 0, d2, nvd, d1, minus1, T + d1 * ldt, ldt, Bd, ldb, 1, Bd + d1 * ldb, ldb,
