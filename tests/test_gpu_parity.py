@@ -459,6 +459,28 @@ def test_pluq_tall_and_wide_generic_panels(lib, orc, p):
         _pluq_compare(lib, orc, A, p, 0, f"generic panels {m}x{n}")
 
 
+@pytest.mark.parametrize("p", [251, 32749, 8388593])
+def test_pluq_int8_paired_panel_products(lib, orc, p):
+    """Generic blocks on the INT8 path whose leading tile exceeds the 256
+    base, so the paired solves run their two inner products (64 x 524 x 512
+    and 724 x 64 x 512 here, ragged in every dimension) as one limb split
+    and one product grid, for one, two and three limbs."""
+    from paper_1402_3501_amd import PATH_INT8
+    rng = np.random.default_rng(p % 997 + 11)
+    m, n = 1300, 1100
+    # A = L U with L unit lower trapezoidal and U upper with a nonzero
+    # diagonal: every leading minor is nonzero, so the whole factorisation
+    # takes the generic path (sums below 1100 p^2 < 2^63)
+    Lm = np.tril(rng.integers(0, p, (m, n), dtype=np.int64), -1)
+    Lm[np.arange(n), np.arange(n)] = 1
+    U = np.triu(rng.integers(0, p, (n, n), dtype=np.int64), 1)
+    U[np.arange(n), np.arange(n)] = rng.integers(1, p, n)
+    A = ((Lm @ U) % p).astype(np.int32)
+    want = orc.pluq(A, p, selfcheck=False)
+    assert np.array_equal(want.P, np.arange(m)) and np.array_equal(want.Q, np.arange(n))
+    _pluq_compare(lib, orc, A, p, PATH_INT8, "int8 paired panel products")
+
+
 def test_pluq_generic_prefix_shortcuts(lib, orc):
     """Rank-deficient inputs whose leading minors are nonzero up to some order
     k0: the failed generic attempt's k0 lets leading tiles within that order
