@@ -187,12 +187,14 @@ __device__ __forceinline__ uint32_t lds_addr(T &x) {
 // The product: a BM x BN block of C per workgroup of NT threads, wave tiles
 // of WM rows.  The K tiles come into LDS by the direct loads of gfx950
 // (global_load_lds_dwordx4: one wave instruction writes 64 consecutive
-// 16-byte chunks, 1 KiB = 16 rows of 64 bytes), three buffers deep: tile t + 2 is requested right after the barrier that opens tile t,
-// so every tile's loads have two tiles' products to arrive, and no registers
-// stage them.  Rows are unpadded; chunk q of tile row r sits at position
-// q ^ ((r / 4) % 4), so that each 16-lane group of a fragment read (16 rows,
-// one chunk) covers all 64 banks once.  The wait before each barrier counts
-// this wave's loads: at most one tile's (the next) may still be in flight.
+// 16-byte chunks, 1 KiB = 16 rows of 64 bytes), three buffers deep: tile
+// t + 2 is requested in the step of tile t, right after its first fragment
+// reads, so every tile's loads have two tiles' products to arrive, and no
+// registers stage them.  Rows are unpadded; chunk q of tile row r sits at
+// position q ^ ((r / 4) % 4), so that each 16-lane group of a fragment read
+// (16 rows, one chunk) covers all 64 banks once.  The wait before each
+// barrier counts this wave's loads: at most one tile's (the next) may still
+// be in flight.
 // One grid may run two products of the same K (the two panel products of a
 // generic node's solves): workgroups [0, g0) take P0, the rest P1.
 struct I8Prod {
@@ -219,8 +221,7 @@ __global__ __launch_bounds__(NT) void k_fgemm_i8(I8Prod P0, I8Prod P1, int g0, i
     static_assert(CHW <= 63, "wait count");
     typedef int8_t TileA[L][BM][BK];
     typedef int8_t TileB[L][BN][BK];
-    // one object per buffer: the compiler then sees that the loads into one
-    // buffer do not alias the fragment reads of another
+    // the three buffers of each operand
     __shared__ __attribute__((aligned(1024))) TileA A0, A1, A2;
     __shared__ __attribute__((aligned(1024))) TileB B0, B1, B2;
 
