@@ -46,7 +46,7 @@ typedef void *ffp_stream_t; /* hipStream_t */
 #define FFP_E_WORKSPACE (-103)   /* workspace missing or too small */
 #define FFP_E_HIP (-104)         /* a HIP runtime call failed */
 #define FFP_E_RANGE (-105)       /* an input entry lies outside [0, p) (ffp_check_range only) */
-#define FFP_E_UNSUPPORTED (-106) /* valid request this build does not implement */
+#define FFP_E_UNSUPPORTED (-106) /* valid request the library does not implement */
 #define FFP_E_NODEVICE (-107)    /* no gfx950 device / kernels failed to load */
 #define FFP_E_INTERNAL (-108)    /* internal consistency check failed; A is restored */
 #define FFP_E_SCRATCH (-109)     /* request exceeds the fixed scratch of ffp_fgemm_noalloc */
