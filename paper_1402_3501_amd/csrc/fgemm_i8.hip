@@ -123,15 +123,17 @@ __global__ __launch_bounds__(256) void k_split(SplitSet set, int64_t K, int64_t 
 
 // ------------------------------------------------------------------ product
 // epilogue: lane l holds rows 4*(l/16)+v, column l%16 of each 16x16 block
-// of the wave tile at (r0, c0); each shift class is reduced, recombined with
-// its weight 256^s mod p, then alpha, beta and the store (or the partial
-// result of K part z)
+// of the wave tile at (r0, c0).  The shift classes S_s (|S_s| < 2^31) are
+// recombined by Horner's rule, t = (..(S_{NS-1} 256 + S_{NS-2}) 256 ..) + S_0,
+// exact in doubles with one reduction after the third class when there are
+// five (2^31 256^2 < 2^48 before it, (p/2 + p) 256^2 + 2^31 256 < 2^48 after
+// it), then reduced; alpha = p - 1 (the C - A B of the factorisations) is a
+// negation; then beta and the store (or the partial result of K part z)
 template <int NS, int FM, int FN>
 __device__ __forceinline__ void i8_epilogue(const v4i (&acc)[NS][FM][FN], int64_t r0, int64_t c0, int lane, int64_t m,
                                             int64_t n, int32_t *__restrict__ C, int64_t ldc, double p, double pinv,
-                                            double alpha, double beta, double w1, double w2, double w3, double w4,
-                                            int z, int32_t *__restrict__ part) {
-    const double w[5] = {1.0, w1, w2, w3, w4};
+                                            double alpha, double beta, int z, int32_t *__restrict__ part) {
+    const bool negate = alpha == p - 1.0;
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
 #pragma unroll
@@ -141,15 +143,25 @@ __device__ __forceinline__ void i8_epilogue(const v4i (&acc)[NS][FM][FN], int64_
             for (int v = 0; v < 4; ++v) {
                 const int64_t gi = r0 + i * 16 + (lane >> 4) * 4 + v;
                 if (gi < m && gj < n) {
-                    double t = 0.0;
+                    double t = (double)acc[NS - 1][i][j][v];
 #pragma unroll
-                    for (int s = 0; s < NS; ++s) t = fma(mod_near((double)acc[s][i][j][v], p, pinv), w[s], t);
+                    for (int s = NS - 2; s >= 0; --s) {
+                        t = fma(t, 256.0, (double)acc[s][i][j][v]);
+                        if (NS == 5 && s == 2) t = mod_near(t, p, pinv);
+                    }
                     double rres = mod_canon(t, p, pinv);
                     if (part) {
                         part[((int64_t)z * m + gi) * n + gj] = (int32_t)rres;
                         continue;
                     }
-                    if (alpha != 1.0) rres = mod_canon(alpha * rres, p, pinv);
+                    if (negate && beta == 1.0) {
+                        // C - A B: both terms canonical, one correction
+                        const double r = (double)C[gi * ldc + gj] - rres;
+                        C[gi * ldc + gj] = (int32_t)(r < 0.0 ? r + p : r);
+                        continue;
+                    }
+                    if (negate) rres = rres == 0.0 ? 0.0 : p - rres;
+                    else if (alpha != 1.0) rres = mod_canon(alpha * rres, p, pinv);
                     if (beta != 0.0) {
                         double c = (double)C[gi * ldc + gj];
                         if (beta != 1.0) c = mod_canon(beta * c, p, pinv);
@@ -206,8 +218,8 @@ struct I8Prod {
 };
 template <int L, int BM, int BN, int NT, int WM>
 __global__ __launch_bounds__(NT) void k_fgemm_i8(I8Prod P0, I8Prod P1, int g0, int64_t Kp, double p, double pinv,
-                                                 double alpha, double beta, double w1, double w2, double w3, double w4,
-                                                 int64_t kt_per, int32_t *__restrict__ part) {
+                                                 double alpha, double beta, int64_t kt_per,
+                                                 int32_t *__restrict__ part) {
     constexpr int BK = 64;
     constexpr int NS = 2 * L - 1;
     constexpr int NW = NT / 64;
@@ -319,8 +331,7 @@ __global__ __launch_bounds__(NT) void k_fgemm_i8(I8Prod P0, I8Prod P1, int g0, i
     }
     // no load may still write the LDS when the workgroup ends
     __builtin_amdgcn_s_waitcnt((0x7 << 4) | (0xF << 8));
-    i8_epilogue<NS, FM, FN>(acc, m0 + wm0, n0 + wn0, lane, m, n, C, ldc, p, pinv, alpha, beta, w1, w2, w3, w4, z,
-                            part);
+    i8_epilogue<NS, FM, FN>(acc, m0 + wm0, n0 + wn0, lane, m, n, C, ldc, p, pinv, alpha, beta, z, part);
 }
 
 // C <- alpha * (sum of the nz partial results) + beta * C, all mod p (each
@@ -403,14 +414,6 @@ static int run_i8(const Field &F, int ta, int tb, int64_t k, uint32_t alpha, uin
         Mp[i] = plane_rows(L, cs[i].m);
         Np[i] = plane_rows(L, cs[i].n);
     }
-    double wts[4] = {0, 0, 0, 0};
-    {
-        uint64_t x = 1;
-        for (int i = 0; i < 4; ++i) {
-            x = (x * 256u) % F.p;
-            wts[i] = (double)x;
-        }
-    }
     // output blocks: 128 x 128 when they fill the chip's 256 compute units,
     // else 64 x 64 (measured on MI355X: 1024^3 with three limbs 31 us against
     // 36 us, the 16384 factorisation 34.3 against 35.0 ms); one limb takes
@@ -491,17 +494,17 @@ static int run_i8(const Field &F, int ta, int tb, int64_t k, uint32_t alpha, uin
                 if (wide)
                     hipLaunchKernelGGL((k_fgemm_i8<1, kI8WideB, kI8WideB, kI8Threads, 64>), dim3((unsigned)grid),
                                        dim3(kI8Threads), 0, s, P[0], P1, g0, Kp, F.pd, F.pinv, (double)alpha, be,
-                                       wts[0], wts[1], wts[2], wts[3], kt_per, part);
+                                       kt_per, part);
             }
             if (wide) {
             } else if (small)
                 hipLaunchKernelGGL((k_fgemm_i8<L, kI8SmallB, kI8SmallB, kI8SmallThreads, 32>), dim3((unsigned)grid),
                                    dim3(kI8SmallThreads), 0, s, P[0], P1, g0, Kp, F.pd, F.pinv, (double)alpha, be,
-                                   wts[0], wts[1], wts[2], wts[3], kt_per, part);
+                                   kt_per, part);
             else
                 hipLaunchKernelGGL((k_fgemm_i8<L, kI8BM, kI8BN, kI8Threads, 32>), dim3((unsigned)grid),
-                                   dim3(kI8Threads), 0, s, P[0], P1, g0, Kp, F.pd, F.pinv, (double)alpha, be, wts[0],
-                                   wts[1], wts[2], wts[3], kt_per, part);
+                                   dim3(kI8Threads), 0, s, P[0], P1, g0, Kp, F.pd, F.pinv, (double)alpha, be,
+                                   kt_per, part);
         }
         if (part) {
             ProfScope prof(PK_I8_COMBINE, 0.0, s, 4.0 * ((double)nz + (be != 0.0 ? 2.0 : 1.0)) * (double)m0 * (double)n0);
